@@ -1,0 +1,238 @@
+/*
+ * xresize.h - C ABI of libxresize.so, bilinear and Keys-bicubic image resize
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper section II.B, eqs. 1-5, generalised to 4x4 taps).
+ * Along each axis an output index x of an image resized from N_in to N_out
+ * samples reads the source at the half-pixel coordinate
+ *     s(x) = ((2x + 1) N_in - N_out) / (2 N_out)          (eq. 1)
+ * with base tap x0 = floor(s) and offset t = s - x0        (eqs. 2-4)
+ * evaluated from exact integers. Bilinear takes taps x0, x0+1 with weights
+ * (1 - t, t); bicubic takes x0-1 .. x0+2 with the Keys (1981) cubic weights
+ * for a = -1/2. Each tap index is clamped to [0, N_in - 1]. Per channel the
+ * output is sum_j wy_j * (sum_i wx_i * src[y0+j][x0+i])     (eq. 5)
+ * in float32: the inner sum over columns first, taps in ascending order, then
+ * the sum over rows in ascending order. That order is the same in every
+ * kernel of the library, so a pixel's value never depends on the tile shape,
+ * the launch, the band split or the batch it was computed in.
+ * uint8 outputs are rounded half-to-even and clamped to [0, 255]; float16
+ * outputs are rounded to nearest even; float32 outputs are stored as is.
+ *
+ * Conventions for every entry point:
+ *  - Image pointers are DEVICE pointers owned by the caller. The library never
+ *    frees or retains them.
+ *  - `stream` is a hipStream_t (NULL = the null stream). Work is enqueued and
+ *    the call returns without synchronising.
+ *  - The resize, batched and backward calls allocate nothing and may be
+ *    captured into a HIP graph; xr_batch_prepare and xr_autotune may not.
+ *  - Every argument is validated on the host before any HIP call. A non-zero
+ *    return value is an XR_ERR_* code; xr_last_error() then gives a
+ *    description (thread-local). No exception crosses the ABI.
+ */
+#ifndef XRESIZE_H
+#define XRESIZE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------ */
+#define XR_OK 0
+#define XR_ERR_NULL 1       /* a required pointer is NULL                          */
+#define XR_ERR_SHAPE 2      /* a size <= 0, a side > XR_MAX_SIDE, planes < 1         */
+#define XR_ERR_DTYPE 3      /* unsupported dtype, or src/dst dtypes differ           */
+#define XR_ERR_CHANNELS 4   /* channels not 1 or 4, or src/dst channels differ       */
+#define XR_ERR_PITCH 5      /* row/plane pitch too small or misaligned               */
+#define XR_ERR_RANGE 6      /* band outside the image, or src band misses needed rows */
+#define XR_ERR_ALIAS 7      /* src and dst memory ranges overlap                     */
+#define XR_ERR_WORKSPACE 8  /* workspace NULL, too small or misaligned               */
+#define XR_ERR_CAPTURE 9    /* a non-capturable call was made on a capturing stream  */
+#define XR_ERR_HIP 10       /* a HIP runtime call failed; see xr_last_error()        */
+#define XR_ERR_ARG 11       /* any other invalid argument (filter, tile, count)      */
+
+/* ---- element types, filters, limits ------------------------------------ */
+#define XR_U8 0
+#define XR_F16 1
+#define XR_F32 2
+
+#define XR_BILINEAR 0
+#define XR_BICUBIC 1
+
+#define XR_MAX_SIDE 32768   /* largest width/height of any image (keeps (2x+1)N in int32) */
+
+/*
+ * Image descriptor. Pixels are row-major with `channels` interleaved values
+ * per pixel (HWC). Planar data (NCHW) is described with channels = 1 and
+ * planes = N*C. `data` points at the first stored row of plane 0, which is
+ * logical row `row0`; rows [row0, row0 + rows) of every plane are stored.
+ * `width` and `height` are always the FULL logical sizes: the coordinate map
+ * of eq. 1 uses them, so a band computes exactly the rows of the whole image.
+ * For a whole image: row0 = 0, rows = height.
+ */
+typedef struct {
+    void *data;          /* device pointer, caller-owned                     */
+    int32_t width;       /* logical width in pixels                          */
+    int32_t height;      /* logical height in pixels                         */
+    int32_t channels;    /* 1 or 4                                           */
+    int32_t dtype;       /* XR_U8, XR_F16, XR_F32                            */
+    int64_t row_pitch;   /* bytes between rows, >= width*channels*elem_size, */
+                         /* multiple of the element size                     */
+    int32_t planes;      /* >= 1                                             */
+    int64_t plane_pitch; /* bytes between planes, >= rows*row_pitch (planes>1) */
+    int32_t row0;        /* first logical row held in `data`                 */
+    int32_t rows;        /* number of logical rows held in `data`            */
+} xr_image;
+
+/*
+ * Launch shape. A workgroup has block_w x block_h threads; each thread
+ * computes ppt_x adjacent output columns and ppt_y output rows, so a tile
+ * covers (block_w*ppt_x) x (block_h*ppt_y) output pixels (eq. 6 with
+ * b_width = block_w*ppt_x, b_height = block_h*ppt_y).
+ *  kernel = XR_KERNEL_AUTO    : use the tuned (or default) shape; other fields ignored
+ *         = XR_KERNEL_GATHER  : one thread per pixel group, every tap read from
+ *                               memory (the paper's block tiling); ppt_x = ppt_y = 1
+ *         = XR_KERNEL_STRIP   : each thread walks ppt_y rows down a strip of
+ *                               ppt_x columns and reuses the filtered rows
+ *                               from registers; block_w a multiple of 64 and
+ *                               block_w * block_h <= 256. An exact x2 upscale
+ *                               on both axes runs a variant specialised for it.
+ *         = XR_KERNEL_STRIP_ANY : the strip kernel without the x2 variant (the
+ *                               same results; for comparisons)
+ */
+#define XR_KERNEL_AUTO 0
+#define XR_KERNEL_GATHER 1
+#define XR_KERNEL_STRIP 2
+#define XR_KERNEL_STRIP_ANY 3
+
+typedef struct {
+    int32_t kernel;
+    int32_t block_w;
+    int32_t block_h;
+    int32_t ppt_x;
+    int32_t ppt_y;
+} xr_tile;
+
+/*
+ * Forward resize, bilinear (paper eqs. 1-5 with half-pixel centres and
+ * clamp-to-edge taps). Computes dst rows [dst->row0, dst->row0 + dst->rows)
+ * of every plane. src and dst must agree in dtype, channels and planes; the
+ * src band must hold every source row those output rows read (rows
+ * floor(s(first)) .. floor(s(last)) + 1, clamped), else XR_ERR_RANGE.
+ * `tile` = NULL or kernel = XR_KERNEL_AUTO selects the tuned shape.
+ */
+int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream);
+
+/*
+ * Forward resize, Keys bicubic with a = -1/2, 4x4 taps per output pixel
+ * (paper section II.B names bicubic interpolation; the kernel is Keys 1981).
+ * Same contract as xr_resize_bilinear; the src band must hold source rows
+ * floor(s(first)) - 1 .. floor(s(last)) + 2, clamped. No antialiasing when
+ * shrinking: the 4 taps are used at every scale.
+ */
+int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream);
+
+/*
+ * Batched resize of many images of uneven sizes and scales in ONE persistent
+ * launch (the paper's per-image tiling question asked for a whole batch,
+ * section III.B).
+ *
+ * xr_batch_workspace_bytes(n): bytes of device workspace for n jobs.
+ * xr_batch_prepare: validates every job exactly like xr_resize_*, splits
+ *   every output into tiles of `tile` (NULL = default shape), orders the jobs
+ *   largest-first, and uploads the job table and tile prefix sums to
+ *   `dev_ws` (device memory, 256-byte aligned, >= xr_batch_workspace_bytes(n))
+ *   with an asynchronous copy on `stream`. The host copy of `jobs` may be
+ *   reused once the call returns. NOT capturable (XR_ERR_CAPTURE).
+ *   All jobs must share one dtype.
+ * xr_resize_batched: one launch that processes every tile of every prepared
+ *   job. Capturable and replayable; it allocates nothing. The workspace must
+ *   not be used by two launches at the same time.
+ * Each output pixel is bit-identical to the one xr_resize_bilinear /
+ * xr_resize_bicubic writes for the same job.
+ */
+typedef struct {
+    xr_image src;
+    xr_image dst;
+    int32_t filter;    /* XR_BILINEAR or XR_BICUBIC */
+} xr_job;
+
+size_t xr_batch_workspace_bytes(int32_t n_jobs);
+int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *dev_ws,
+                     size_t ws_bytes, void *stream);
+int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
+
+/*
+ * Adjoint of the resize with respect to its input: grad_src = A^T grad_dst,
+ * where A is the linear map of the forward call with the same filter and
+ * sizes; every output pixel scatters wy_j * wx_i * g onto its clamped taps
+ * (the transpose of eq. 5). float32, whole images only (row0 = 0,
+ * rows = height on both), planes map one to one, channels 1 or 4.
+ * grad_src is OVERWRITTEN. Contributions are summed in LDS per output tile and
+ * merged across tiles with float32 atomics, so the summation order (not the
+ * set of terms) may differ between runs.
+ */
+int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32_t filter,
+                       void *stream);
+
+/*
+ * Launch-shape tuning (the paper's tiling question, section IV, measured on
+ * this GPU). Times every candidate with HIP events on the given images
+ * (`reps` launches per candidate after one warm-up, median of `groups`
+ * groups), writes the fastest to *best and its mean time per launch in ms to
+ * *best_ms (either may be NULL), and remembers it for later XR_KERNEL_AUTO
+ * calls with the same key (filter, dtype, channels, scale class). Overwrites
+ * dst. candidates = NULL uses the built-in candidate list. Synchronises the
+ * stream; NOT capturable.
+ * xr_tune_candidates: copies up to `cap` built-in candidates for the given
+ * key into `out` and returns how many exist.
+ */
+int xr_autotune(const xr_image *src, const xr_image *dst, int32_t filter, const xr_tile *candidates,
+                int32_t n_candidates, int32_t reps, int32_t groups, xr_tile *best, float *best_ms,
+                void *stream);
+int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w,
+                           int32_t in_h, int32_t out_w, int32_t out_h, xr_tile *out, int32_t cap);
+
+/*
+ * The shape XR_KERNEL_AUTO resolves to for a key: the tuned one if
+ * xr_autotune (or xr_set_tile) stored one, else the built-in default.
+ */
+int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
+                int32_t out_w, int32_t out_h, xr_tile *out);
+int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
+                int32_t out_w, int32_t out_h, const xr_tile *tile);
+
+/*
+ * Host-side geometry (no HIP call; usable without a GPU).
+ * xr_source_taps: for output index x of an axis n_in -> n_out, the base tap
+ *   x0 = floor(s(x)) and the numerator / denominator of t = num/den (eqs. 1-4).
+ * xr_needed_rows: inclusive range of clamped source rows that output rows
+ *   [row0, row0 + rows) read.
+ * xr_thread_of_pixel: eq. 6 inverted for a tile shape: the workgroup
+ *   (block_x, block_y) and the thread (thread_x, thread_y) that compute output
+ *   pixel (px, py), plus the pixel's index within that thread's ppt_x x ppt_y
+ *   group (sub_x, sub_y).
+ */
+int xr_source_taps(int32_t n_in, int32_t n_out, int32_t x, int32_t *x0, int64_t *t_num,
+                   int64_t *t_den);
+int xr_needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
+                   int32_t *first, int32_t *last);
+int xr_thread_of_pixel(const xr_tile *tile, int32_t px, int32_t py, int32_t *block_x,
+                       int32_t *block_y, int32_t *thread_x, int32_t *thread_y, int32_t *sub_x,
+                       int32_t *sub_y);
+
+/* Strings. xr_strerror never returns NULL; xr_last_error is thread-local and
+ * describes the most recent failing call on the calling thread. */
+const char *xr_strerror(int code);
+const char *xr_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int xr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XRESIZE_H */

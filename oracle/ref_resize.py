@@ -98,18 +98,25 @@ def _as_planes(img) -> np.ndarray:
     return img.astype(np.float64)
 
 
-def resize_rows(img, out_h: int, out_w: int, rows, filt: int, a: float = KEYS_A) -> np.ndarray:
+def resize_rows(img, out_h: int, out_w: int, rows, filt: int, a: float = KEYS_A,
+                absolute: bool = False) -> np.ndarray:
     """Output rows ``rows`` of the resize of ``img`` (P, H, W, C) to (out_h, out_w).
 
     Returns float64 of shape (P, len(rows), out_w, C). Direct double sum over
-    the taps of each output pixel (eq. 5 generalised).
+    the taps of each output pixel (eq. 5 generalised). With ``absolute`` the
+    sum is taken over |w_y w_x src| instead: the scale of the rounding error of
+    any evaluation of the same sum.
     """
     src = _as_planes(img)
+    if absolute:
+        src = np.abs(src)
     _, in_h, in_w, _ = src.shape
     rows = np.asarray(rows, dtype=np.int64)
     iy, wy, _, _ = axis_taps(in_h, out_h, filt, a)
     ix, wx, _, _ = axis_taps(in_w, out_w, filt, a)
     iy, wy = iy[rows], wy[rows]
+    if absolute:
+        wy, wx = np.abs(wy), np.abs(wx)
     out = np.zeros((src.shape[0], rows.size, out_w, src.shape[3]), dtype=np.float64)
     k = iy.shape[1]
     for j in range(k):
@@ -125,16 +132,22 @@ def resize(img, out_h: int, out_w: int, filt: int, a: float = KEYS_A) -> np.ndar
     return resize_rows(img, out_h, out_w, np.arange(out_h), filt, a)
 
 
-def adjoint(grad_out, in_h: int, in_w: int, filt: int, a: float = KEYS_A) -> np.ndarray:
+def adjoint(grad_out, in_h: int, in_w: int, filt: int, a: float = KEYS_A,
+            absolute: bool = False) -> np.ndarray:
     """Adjoint of ``resize`` with respect to its input.
 
     grad_out has shape (P, out_h, out_w, C); returns float64 (P, in_h, in_w, C)
     with grad_src[p, clamp(y0+j), clamp(x0+i), c] += wy_j wx_i grad_out[p, y, x, c].
+    With ``absolute`` it accumulates |wy_j wx_i g| (the rounding-error scale).
     """
     g = _as_planes(grad_out)
+    if absolute:
+        g = np.abs(g)
     planes, out_h, out_w, ch = g.shape
     iy, wy, _, _ = axis_taps(in_h, out_h, filt, a)
     ix, wx, _, _ = axis_taps(in_w, out_w, filt, a)
+    if absolute:
+        wy, wx = np.abs(wy), np.abs(wx)
     gs = np.zeros((planes, in_h, in_w, ch), dtype=np.float64)
     k = iy.shape[1]
     for j in range(k):

@@ -1,0 +1,130 @@
+"""ctypes binding of libxresize.so (include/xresize.h): argument marshalling only.
+
+Every computation happens in the HIP library. If the library is not built the
+import of this module fails; there is no fallback implementation.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY = os.path.join(HERE, "libxresize.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "xresize.h")
+
+XR_OK = 0
+XR_ERR_NULL = 1
+XR_ERR_SHAPE = 2
+XR_ERR_DTYPE = 3
+XR_ERR_CHANNELS = 4
+XR_ERR_PITCH = 5
+XR_ERR_RANGE = 6
+XR_ERR_ALIAS = 7
+XR_ERR_WORKSPACE = 8
+XR_ERR_CAPTURE = 9
+XR_ERR_HIP = 10
+XR_ERR_ARG = 11
+
+XR_U8, XR_F16, XR_F32 = 0, 1, 2
+XR_BILINEAR, XR_BICUBIC = 0, 1
+XR_MAX_SIDE = 32768
+XR_KERNEL_AUTO, XR_KERNEL_GATHER, XR_KERNEL_STRIP, XR_KERNEL_STRIP_ANY = 0, 1, 2, 3
+
+
+class XrImage(ctypes.Structure):
+    _fields_ = [
+        ("data", ctypes.c_void_p),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("channels", ctypes.c_int32),
+        ("dtype", ctypes.c_int32),
+        ("row_pitch", ctypes.c_int64),
+        ("planes", ctypes.c_int32),
+        ("plane_pitch", ctypes.c_int64),
+        ("row0", ctypes.c_int32),
+        ("rows", ctypes.c_int32),
+    ]
+
+
+class XrTile(ctypes.Structure):
+    _fields_ = [
+        ("kernel", ctypes.c_int32),
+        ("block_w", ctypes.c_int32),
+        ("block_h", ctypes.c_int32),
+        ("ppt_x", ctypes.c_int32),
+        ("ppt_y", ctypes.c_int32),
+    ]
+
+    def as_tuple(self):
+        return (self.kernel, self.block_w, self.block_h, self.ppt_x, self.ppt_y)
+
+    def __repr__(self):
+        kind = {0: "auto", 1: "gather", 2: "strip", 3: "strip_any"}.get(self.kernel, str(self.kernel))
+        return (f"XrTile({kind}, block={self.block_w}x{self.block_h}, "
+                f"ppt={self.ppt_x}x{self.ppt_y})")
+
+
+class XrJob(ctypes.Structure):
+    _fields_ = [("src", XrImage), ("dst", XrImage), ("filter", ctypes.c_int32)]
+
+
+class XResizeError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {strerror(code)} ({code}): {detail}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIBRARY):
+        raise ImportError(f"{LIBRARY} is not built: run `python -m paper_1001_1718_amd.build_lib` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIBRARY)
+    i32, i64, vp, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t
+    pimg, ptile = ctypes.POINTER(XrImage), ctypes.POINTER(XrTile)
+    pi32, pi64 = ctypes.POINTER(i32), ctypes.POINTER(i64)
+    sigs = {
+        "xr_resize_bilinear": (ctypes.c_int, [pimg, pimg, ptile, vp]),
+        "xr_resize_bicubic": (ctypes.c_int, [pimg, pimg, ptile, vp]),
+        "xr_batch_workspace_bytes": (sz, [i32]),
+        "xr_batch_prepare": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, vp, sz, vp]),
+        "xr_resize_batched": (ctypes.c_int, [vp, i32, vp]),
+        "xr_resize_backward": (ctypes.c_int, [pimg, pimg, i32, vp]),
+        "xr_autotune": (ctypes.c_int, [pimg, pimg, i32, ptile, i32, i32, i32, ptile,
+                                       ctypes.POINTER(ctypes.c_float), vp]),
+        "xr_tune_candidates": (i32, [i32, i32, i32, i32, i32, i32, i32, ptile, i32]),
+        "xr_get_tile": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, i32, ptile]),
+        "xr_set_tile": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, i32, ptile]),
+        "xr_source_taps": (ctypes.c_int, [i32, i32, i32, pi32, pi64, pi64]),
+        "xr_needed_rows": (ctypes.c_int, [i32, i32, i32, i32, i32, pi32, pi32]),
+        "xr_thread_of_pixel": (ctypes.c_int, [ptile, i32, i32, pi32, pi32, pi32, pi32, pi32, pi32]),
+        "xr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+        "xr_last_error": (ctypes.c_char_p, []),
+        "xr_version": (ctypes.c_int, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def strerror(code: int) -> str:
+    return lib.xr_strerror(int(code)).decode()
+
+
+def last_error() -> str:
+    return lib.xr_last_error().decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != XR_OK:
+        raise XResizeError(code, where, last_error())
+
+
+def tile(kernel: int = XR_KERNEL_AUTO, block_w: int = 0, block_h: int = 0, ppt_x: int = 1,
+         ppt_y: int = 1) -> XrTile:
+    return XrTile(int(kernel), int(block_w), int(block_h), int(ppt_x), int(ppt_y))

@@ -1,0 +1,759 @@
+// C-ABI layer of libxresize.so: argument validation (always before any HIP
+// call), launch-shape selection, the batched job table, tuning, and error
+// reporting. The kernels live in xr_forward.hip and xr_backward.hip.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/xresize.h"
+#include "xr_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(XR_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+}
+
+int elem_size(int32_t dtype)
+{
+    switch (dtype) {
+    case XR_U8:
+        return 1;
+    case XR_F16:
+        return 2;
+    case XR_F32:
+        return 4;
+    default:
+        return 0;
+    }
+}
+
+// ---- exact host geometry (eqs. 1-4) ------------------------------------
+
+int64_t floor_div(int64_t a, int64_t b)
+{
+    int64_t q = a / b;
+    if ((a % b != 0) && ((a < 0) != (b < 0)))
+        --q;
+    return q;
+}
+
+// x0 = floor(s(x)) for s(x) = ((2x+1) n_in - n_out) / (2 n_out)
+int64_t base_tap(int64_t x, int64_t n_in, int64_t n_out)
+{
+    return floor_div((2 * x + 1) * n_in - n_out, 2 * n_out);
+}
+
+int taps_of(int32_t filter) { return filter == XR_BICUBIC ? 4 : 2; }
+int first_offset(int32_t filter) { return filter == XR_BICUBIC ? -1 : 0; }
+
+void needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
+                 int32_t *first, int32_t *last)
+{
+    const int64_t lo = base_tap(row0, in_h, out_h) + first_offset(filter);
+    const int64_t hi = base_tap(row0 + rows - 1, in_h, out_h) + first_offset(filter) + taps_of(filter) - 1;
+    *first = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(lo, 0), in_h - 1));
+    *last = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(hi, 0), in_h - 1));
+}
+
+// ---- validation ---------------------------------------------------------
+
+int64_t image_extent(const xr_image &im)
+{
+    const int64_t row_bytes = static_cast<int64_t>(im.width) * im.channels * elem_size(im.dtype);
+    return static_cast<int64_t>(im.planes - 1) * im.plane_pitch +
+           static_cast<int64_t>(im.rows - 1) * im.row_pitch + row_bytes;
+}
+
+int check_image(const xr_image *im, const char *name)
+{
+    if (!im)
+        return fail(XR_ERR_NULL, "%s descriptor is NULL", name);
+    if (!im->data)
+        return fail(XR_ERR_NULL, "%s.data is NULL", name);
+    if (im->width < 1 || im->height < 1 || im->width > XR_MAX_SIDE || im->height > XR_MAX_SIDE)
+        return fail(XR_ERR_SHAPE, "%s size %dx%d outside 1..%d", name, im->width, im->height,
+                    XR_MAX_SIDE);
+    if (im->planes < 1 || im->planes > 65535)
+        return fail(XR_ERR_SHAPE, "%s.planes = %d outside 1..65535", name, im->planes);
+    const int es = elem_size(im->dtype);
+    if (es == 0)
+        return fail(XR_ERR_DTYPE, "%s.dtype = %d is not XR_U8, XR_F16 or XR_F32", name, im->dtype);
+    if (im->channels != 1 && im->channels != 4)
+        return fail(XR_ERR_CHANNELS, "%s.channels = %d (must be 1 or 4)", name, im->channels);
+    if (im->rows < 1 || im->row0 < 0 || static_cast<int64_t>(im->row0) + im->rows > im->height)
+        return fail(XR_ERR_RANGE, "%s band rows [%d, %d) outside [0, %d)", name, im->row0,
+                    im->row0 + im->rows, im->height);
+    const int64_t px = static_cast<int64_t>(im->channels) * es;
+    const int64_t row_bytes = px * im->width;
+    if (im->row_pitch < row_bytes || im->row_pitch % px != 0)
+        return fail(XR_ERR_PITCH, "%s.row_pitch = %lld (need >= %lld, multiple of %lld)", name,
+                    static_cast<long long>(im->row_pitch), static_cast<long long>(row_bytes),
+                    static_cast<long long>(px));
+    if (im->planes > 1) {
+        const int64_t need = static_cast<int64_t>(im->rows - 1) * im->row_pitch + row_bytes;
+        if (im->plane_pitch < need || im->plane_pitch % px != 0)
+            return fail(XR_ERR_PITCH, "%s.plane_pitch = %lld (need >= %lld, multiple of %lld)", name,
+                        static_cast<long long>(im->plane_pitch), static_cast<long long>(need),
+                        static_cast<long long>(px));
+    }
+    if (reinterpret_cast<uintptr_t>(im->data) % static_cast<uintptr_t>(px) != 0)
+        return fail(XR_ERR_PITCH, "%s.data is not aligned to the %lld-byte pixel", name,
+                    static_cast<long long>(px));
+    return XR_OK;
+}
+
+bool overlaps(const xr_image &a, const xr_image &b)
+{
+    const uintptr_t a0 = reinterpret_cast<uintptr_t>(a.data);
+    const uintptr_t b0 = reinterpret_cast<uintptr_t>(b.data);
+    const uintptr_t a1 = a0 + static_cast<uintptr_t>(image_extent(a));
+    const uintptr_t b1 = b0 + static_cast<uintptr_t>(image_extent(b));
+    return a0 < b1 && b0 < a1;
+}
+
+int check_pair(const xr_image *src, const xr_image *dst, int32_t filter)
+{
+    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+        return fail(XR_ERR_ARG, "filter = %d is not XR_BILINEAR or XR_BICUBIC", filter);
+    int rc = check_image(src, "src");
+    if (rc)
+        return rc;
+    rc = check_image(dst, "dst");
+    if (rc)
+        return rc;
+    if (src->dtype != dst->dtype)
+        return fail(XR_ERR_DTYPE, "src.dtype %d != dst.dtype %d", src->dtype, dst->dtype);
+    if (src->channels != dst->channels)
+        return fail(XR_ERR_CHANNELS, "src.channels %d != dst.channels %d", src->channels,
+                    dst->channels);
+    if (src->planes != dst->planes)
+        return fail(XR_ERR_SHAPE, "src.planes %d != dst.planes %d", src->planes, dst->planes);
+    int32_t first, last;
+    needed_rows(src->height, dst->height, dst->row0, dst->rows, filter, &first, &last);
+    if (first < src->row0 || last > src->row0 + src->rows - 1)
+        return fail(XR_ERR_RANGE, "output rows [%d, %d) read source rows %d..%d but src holds [%d, %d)",
+                    dst->row0, dst->row0 + dst->rows, first, last, src->row0,
+                    src->row0 + src->rows);
+    if (overlaps(*src, *dst))
+        return fail(XR_ERR_ALIAS, "src and dst memory overlap");
+    return XR_OK;
+}
+
+xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
+{
+    xr::ResizeArgs a{};
+    a.src = static_cast<const unsigned char *>(src.data);
+    a.dst = static_cast<unsigned char *>(dst.data);
+    a.src_pitch = src.row_pitch;
+    a.src_plane_pitch = src.planes > 1 ? src.plane_pitch : 0;
+    a.dst_pitch = dst.row_pitch;
+    a.dst_plane_pitch = dst.planes > 1 ? dst.plane_pitch : 0;
+    a.in_w = src.width;
+    a.in_h = src.height;
+    a.out_w = dst.width;
+    a.out_h = dst.height;
+    a.src_row0 = src.row0;
+    a.dst_row0 = dst.row0;
+    a.dst_rows = dst.rows;
+    a.planes = src.planes;
+    const auto al = [](const void *p, int64_t v1, int64_t v2) {
+        return reinterpret_cast<uintptr_t>(p) % 16 == 0 && v1 % 16 == 0 && v2 % 16 == 0;
+    };
+    a.aligned16 = al(src.data, a.src_pitch, a.src_plane_pitch) && al(dst.data, a.dst_pitch, a.dst_plane_pitch);
+    return a;
+}
+
+int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t)
+{
+    if (t.kernel != XR_KERNEL_STRIP)
+        return xr::kGeneral;
+    return (dst.width == 2 * src.width && dst.height == 2 * src.height) ? xr::kUp2 : xr::kGeneral;
+}
+
+// ---- launch shapes ------------------------------------------------------
+
+// scale class of one axis: 0 = x2 up exactly, 1 = identity, 2 = other up,
+// 3 = x2 down exactly, 4 = other down
+int scale_class(int32_t n_in, int32_t n_out)
+{
+    if (n_out == 2 * n_in)
+        return 0;
+    if (n_out == n_in)
+        return 1;
+    if (n_out > n_in)
+        return 2;
+    if (n_in == 2 * n_out)
+        return 3;
+    return 4;
+}
+
+using TuneKey = std::tuple<int, int, int, int, int>;
+
+TuneKey tune_key(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
+                 int32_t out_w, int32_t out_h)
+{
+    return TuneKey(filter, dtype, channels, scale_class(in_w, out_w), scale_class(in_h, out_h));
+}
+
+std::mutex g_tune_mu;
+std::map<TuneKey, xr_tile> g_tuned;
+
+xr_tile default_tile(int32_t channels)
+{
+    xr_tile t{};
+    t.kernel = XR_KERNEL_STRIP;
+    t.block_w = 64;
+    t.block_h = 4;
+    t.ppt_x = channels == 4 ? 4 : 8;
+    t.ppt_y = 32;
+    return t;
+}
+
+int check_tile(const xr_tile &t, int32_t dtype, int32_t channels)
+{
+    if (t.kernel == XR_KERNEL_GATHER) {
+        if (t.block_w < 1 || t.block_h < 1 || t.block_w * t.block_h > 1024 || t.ppt_x != 1 ||
+            t.ppt_y != 1)
+            return fail(XR_ERR_ARG, "gather tile %dx%d (ppt %dx%d) invalid: need 1..1024 threads, ppt 1x1",
+                        t.block_w, t.block_h, t.ppt_x, t.ppt_y);
+        return XR_OK;
+    }
+    if (t.kernel == XR_KERNEL_STRIP || t.kernel == XR_KERNEL_STRIP_ANY) {
+        if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256)
+            return fail(XR_ERR_ARG,
+                        "strip tile block %dx%d invalid: block_w a multiple of 64, at most 256 threads",
+                        t.block_w, t.block_h);
+        if (!xr::strip_ppx_supported(dtype, channels, t.ppt_x))
+            return fail(XR_ERR_ARG, "strip ppt_x = %d not built for %d channels", t.ppt_x, channels);
+        if (t.ppt_y < 1 || t.ppt_y > 4096)
+            return fail(XR_ERR_ARG, "strip ppt_y = %d outside 1..4096", t.ppt_y);
+        return XR_OK;
+    }
+    return fail(XR_ERR_ARG, "tile.kernel = %d unknown", t.kernel);
+}
+
+xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, const xr_image &dst)
+{
+    if (tile && tile->kernel != XR_KERNEL_AUTO)
+        return *tile;
+    const TuneKey key = tune_key(filter, src.dtype, src.channels, src.width, src.height, dst.width,
+                                 dst.height);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(key);
+    if (it != g_tuned.end())
+        return it->second;
+    return default_tile(src.channels);
+}
+
+int check_grid(const xr_tile &t, const xr_image &dst)
+{
+    const int64_t rows_per_block = static_cast<int64_t>(t.block_h) * t.ppt_y;
+    const int64_t gy = (dst.rows + rows_per_block - 1) / rows_per_block;
+    if (gy > 65535)
+        return fail(XR_ERR_ARG, "tile too short for %d rows: %lld workgroup rows > 65535", dst.rows,
+                    static_cast<long long>(gy));
+    return XR_OK;
+}
+
+int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile, int32_t filter,
+                  void *stream)
+{
+    int rc = check_pair(src, dst, filter);
+    if (rc)
+        return rc;
+    const xr_tile t = resolve_tile(tile, filter, *src, *dst);
+    rc = check_tile(t, src->dtype, src->channels);
+    if (rc)
+        return rc;
+    rc = check_grid(t, *dst);
+    if (rc)
+        return rc;
+    const xr::ResizeArgs a = make_args(*src, *dst);
+    const hipError_t e = xr::launch_forward(a, filter, src->dtype, src->channels, t,
+                                            axis_mode(*src, *dst, t), static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "resize launch");
+    return XR_OK;
+}
+
+// ---- batched workspaces -------------------------------------------------
+
+struct BatchInfo {
+    int32_t n_jobs;
+    int32_t dtype;
+    int32_t block_w, block_h;
+    int32_t grid;
+};
+std::mutex g_batch_mu;
+std::map<const void *, BatchInfo> g_batches;
+
+}  // namespace
+
+extern "C" {
+
+int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, XR_BILINEAR, stream);
+}
+
+int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, XR_BICUBIC, stream);
+}
+
+size_t xr_batch_workspace_bytes(int32_t n_jobs)
+{
+    if (n_jobs < 1)
+        return 0;
+    return xr::kBatchHeaderBytes + static_cast<size_t>(n_jobs) * sizeof(xr::BatchJob);
+}
+
+int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *dev_ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (!jobs)
+        return fail(XR_ERR_NULL, "jobs is NULL");
+    if (n_jobs < 1)
+        return fail(XR_ERR_ARG, "n_jobs = %d (must be >= 1)", n_jobs);
+    if (!dev_ws)
+        return fail(XR_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+        return fail(XR_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < xr_batch_workspace_bytes(n_jobs))
+        return fail(XR_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                    xr_batch_workspace_bytes(n_jobs));
+    xr_tile t{};
+    if (tile && tile->kernel != XR_KERNEL_AUTO) {
+        t = *tile;
+        if (t.kernel != XR_KERNEL_STRIP)
+            return fail(XR_ERR_ARG, "the batched launch takes a strip tile");
+    } else {
+        t = default_tile(4);
+    }
+    t.ppt_x = xr::kBatchPpx;
+    if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256 ||
+        t.ppt_y < 1 || t.ppt_y > 4096)
+        return fail(XR_ERR_ARG, "batched tile block %dx%d ppt_y %d invalid", t.block_w, t.block_h,
+                    t.ppt_y);
+    const int32_t dtype = jobs[0].src.dtype;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const int rc = check_pair(&jobs[k].src, &jobs[k].dst, jobs[k].filter);
+        if (rc)
+            return fail(rc, "job %d: %s", k, g_last_error.c_str());
+        if (jobs[k].src.dtype != dtype)
+            return fail(XR_ERR_DTYPE, "job %d: dtype %d differs from job 0 (%d)", k, jobs[k].src.dtype,
+                        dtype);
+    }
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const xr_image &d = jobs[k].dst;
+        for (int32_t m = 0; m < n_jobs; ++m)
+            if (overlaps(d, jobs[m].src) || (m != k && overlaps(d, jobs[m].dst)))
+                return fail(XR_ERR_ALIAS, "job %d: dst overlaps job %d's %s", k, m,
+                            m == k ? "src" : (overlaps(d, jobs[m].src) ? "src" : "dst"));
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    hipError_t e = hipStreamIsCapturing(static_cast<hipStream_t>(stream), &cs);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(XR_ERR_CAPTURE, "xr_batch_prepare called on a capturing stream");
+
+    // largest output first
+    std::vector<int32_t> order(n_jobs);
+    for (int32_t k = 0; k < n_jobs; ++k)
+        order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+        const int64_t wp = static_cast<int64_t>(jobs[p].dst.width) * jobs[p].dst.rows * jobs[p].dst.planes;
+        const int64_t wq = static_cast<int64_t>(jobs[q].dst.width) * jobs[q].dst.rows * jobs[q].dst.planes;
+        return wp > wq;
+    });
+    std::vector<unsigned char> host(xr_batch_workspace_bytes(n_jobs), 0);
+    auto *hdr = reinterpret_cast<xr::BatchHeader *>(host.data());
+    auto *tab = reinterpret_cast<xr::BatchJob *>(host.data() + xr::kBatchHeaderBytes);
+    const int64_t tile_w = static_cast<int64_t>(t.block_w) * xr::kBatchPpx;
+    const int64_t tile_h = static_cast<int64_t>(t.block_h) * t.ppt_y;
+    int64_t total = 0;
+    for (int32_t k = 0; k < n_jobs; ++k) {
+        const xr_job &j = jobs[order[k]];
+        xr::BatchJob &b = tab[k];
+        b.a = make_args(j.src, j.dst);
+        b.filter = j.filter;
+        b.channels = j.src.channels;
+        b.tiles_x = static_cast<int32_t>((j.dst.width + tile_w - 1) / tile_w);
+        b.tiles_y = static_cast<int32_t>((j.dst.rows + tile_h - 1) / tile_h);
+        b.tile_begin = total;
+        total += static_cast<int64_t>(b.tiles_x) * b.tiles_y * j.dst.planes;
+    }
+    if (total >= (int64_t(1) << 31))
+        return fail(XR_ERR_ARG, "batch has %lld tiles (limit 2^31)", static_cast<long long>(total));
+    int dev = 0, cus = 0;
+    e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess)
+        return fail_hip(e, "device query");
+    const int32_t per_cu = xr::batched_blocks_per_cu(dtype, t.block_w * t.block_h);
+    const int64_t grid = std::min<int64_t>(static_cast<int64_t>(per_cu) * cus, total);
+    hdr->total_tiles = total;
+    hdr->n_jobs = n_jobs;
+    hdr->dtype = dtype;
+    hdr->block_w = t.block_w;
+    hdr->block_h = t.block_h;
+    hdr->ppt_y = t.ppt_y;
+    hdr->grid = static_cast<int32_t>(std::max<int64_t>(grid, 1));
+    hdr->ticket = 0;
+    hdr->done = 0;
+    e = hipMemcpyAsync(dev_ws, host.data(), host.size(), hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "uploading the job table");
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    g_batches[dev_ws] = BatchInfo{n_jobs, dtype, t.block_w, t.block_h, hdr->grid};
+    return XR_OK;
+}
+
+int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream)
+{
+    if (!dev_ws)
+        return fail(XR_ERR_WORKSPACE, "workspace is NULL");
+    BatchInfo info{};
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mu);
+        auto it = g_batches.find(dev_ws);
+        if (it == g_batches.end())
+            return fail(XR_ERR_WORKSPACE, "workspace was not prepared by xr_batch_prepare");
+        info = it->second;
+    }
+    if (n_jobs != info.n_jobs)
+        return fail(XR_ERR_ARG, "n_jobs = %d but the workspace holds %d jobs", n_jobs, info.n_jobs);
+    const hipError_t e = xr::launch_batched(dev_ws, info.dtype, info.block_w, info.block_h, info.grid,
+                                            static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "batched launch");
+    return XR_OK;
+}
+
+int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32_t filter,
+                       void *stream)
+{
+    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+        return fail(XR_ERR_ARG, "filter = %d is not XR_BILINEAR or XR_BICUBIC", filter);
+    int rc = check_image(grad_dst, "grad_dst");
+    if (rc)
+        return rc;
+    rc = check_image(grad_src, "grad_src");
+    if (rc)
+        return rc;
+    if (grad_dst->dtype != XR_F32 || grad_src->dtype != XR_F32)
+        return fail(XR_ERR_DTYPE, "the adjoint is float32 only");
+    if (grad_dst->channels != grad_src->channels)
+        return fail(XR_ERR_CHANNELS, "grad_dst.channels %d != grad_src.channels %d",
+                    grad_dst->channels, grad_src->channels);
+    if (grad_dst->planes != grad_src->planes)
+        return fail(XR_ERR_SHAPE, "grad_dst.planes %d != grad_src.planes %d", grad_dst->planes,
+                    grad_src->planes);
+    if (grad_dst->row0 != 0 || grad_dst->rows != grad_dst->height || grad_src->row0 != 0 ||
+        grad_src->rows != grad_src->height)
+        return fail(XR_ERR_RANGE, "the adjoint takes whole images (row0 = 0, rows = height)");
+    if (overlaps(*grad_dst, *grad_src))
+        return fail(XR_ERR_ALIAS, "grad_dst and grad_src memory overlap");
+    // forward view: source = grad_src geometry, destination = grad_dst geometry
+    xr::ResizeArgs a = make_args(*grad_src, *grad_dst);
+    a.src = static_cast<const unsigned char *>(grad_dst->data);
+    a.src_pitch = grad_dst->row_pitch;
+    a.src_plane_pitch = grad_dst->planes > 1 ? grad_dst->plane_pitch : 0;
+    a.dst = static_cast<unsigned char *>(grad_src->data);
+    a.dst_pitch = grad_src->row_pitch;
+    a.dst_plane_pitch = grad_src->planes > 1 ? grad_src->plane_pitch : 0;
+    const hipError_t e = xr::launch_backward(a, filter, grad_src->channels, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "backward launch");
+    return XR_OK;
+}
+
+int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w,
+                           int32_t in_h, int32_t out_w, int32_t out_h, xr_tile *out, int32_t cap)
+{
+    (void)filter;
+    (void)in_w;
+    (void)in_h;
+    (void)out_w;
+    (void)out_h;
+    std::vector<xr_tile> c;
+    // the paper's block shapes (W x H threads, one pixel each) and a few wider ones
+    const int gather[][2] = {{8, 8}, {32, 4}, {32, 16}, {4, 8}, {8, 4}, {16, 16}, {64, 4}, {64, 1},
+                             {128, 2}, {256, 1}};
+    for (const auto &g : gather)
+        c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1});
+    const int ppx_list[2] = {channels == 4 ? 2 : 4, channels == 4 ? 4 : 8};
+    const int blocks[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
+    const int ppy_list[] = {8, 16, 32, 64, 128};
+    for (int ppx : ppx_list) {
+        if (!xr::strip_ppx_supported(dtype, channels, ppx))
+            continue;
+        for (const auto &b : blocks)
+            for (int ppy : ppy_list)
+                c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy});
+    }
+    if (out)
+        for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)
+            out[k] = c[k];
+    return static_cast<int32_t>(c.size());
+}
+
+int xr_autotune(const xr_image *src, const xr_image *dst, int32_t filter, const xr_tile *candidates,
+                int32_t n_candidates, int32_t reps, int32_t groups, xr_tile *best, float *best_ms,
+                void *stream)
+{
+    int rc = check_pair(src, dst, filter);
+    if (rc)
+        return rc;
+    if (reps < 1 || groups < 1)
+        return fail(XR_ERR_ARG, "reps = %d, groups = %d (both must be >= 1)", reps, groups);
+    std::vector<xr_tile> cand;
+    if (candidates) {
+        if (n_candidates < 1)
+            return fail(XR_ERR_ARG, "n_candidates = %d", n_candidates);
+        cand.assign(candidates, candidates + n_candidates);
+    } else {
+        const int32_t n = xr_tune_candidates(filter, src->dtype, src->channels, src->width, src->height,
+                                             dst->width, dst->height, nullptr, 0);
+        cand.resize(n);
+        xr_tune_candidates(filter, src->dtype, src->channels, src->width, src->height, dst->width,
+                           dst->height, cand.data(), n);
+    }
+    for (size_t k = 0; k < cand.size(); ++k) {
+        if (cand[k].kernel == XR_KERNEL_AUTO)
+            return fail(XR_ERR_ARG, "candidate %zu is XR_KERNEL_AUTO", k);
+        rc = check_tile(cand[k], src->dtype, src->channels);
+        if (!rc)
+            rc = check_grid(cand[k], *dst);
+        if (rc)
+            return fail(rc, "candidate %zu: %s", k, g_last_error.c_str());
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipStreamIsCapturing(s, &cs);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(XR_ERR_CAPTURE, "xr_autotune called on a capturing stream");
+    hipEvent_t ev0, ev1;
+    if ((e = hipEventCreate(&ev0)) != hipSuccess)
+        return fail_hip(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    const xr::ResizeArgs a = make_args(*src, *dst);
+    float best_t = 0.0f;
+    size_t best_k = 0;
+    bool have = false;
+    std::vector<float> per_group(groups);
+    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        const int32_t mode = axis_mode(*src, *dst, cand[k]);
+        e = xr::launch_forward(a, filter, src->dtype, src->channels, cand[k], mode, s);  // warm-up
+        for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
+            e = hipEventRecord(ev0, s);
+            for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
+                e = xr::launch_forward(a, filter, src->dtype, src->channels, cand[k], mode, s);
+            if (e == hipSuccess)
+                e = hipEventRecord(ev1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, ev0, ev1);
+            per_group[g] = ms / static_cast<float>(reps);
+        }
+        if (e != hipSuccess)
+            break;
+        std::sort(per_group.begin(), per_group.end());
+        const float med = per_group[groups / 2];
+        const int threads = cand[k].block_w * cand[k].block_h;
+        const int best_threads = have ? cand[best_k].block_w * cand[best_k].block_h : 0;
+        if (!have || med < best_t || (med == best_t && threads < best_threads)) {
+            best_t = med;
+            best_k = k;
+            have = true;
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (e != hipSuccess)
+        return fail_hip(e, "timing a candidate");
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tuned[tune_key(filter, src->dtype, src->channels, src->width, src->height, dst->width,
+                         dst->height)] = cand[best_k];
+    }
+    if (best)
+        *best = cand[best_k];
+    if (best_ms)
+        *best_ms = best_t;
+    return XR_OK;
+}
+
+int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
+                int32_t out_w, int32_t out_h, xr_tile *out)
+{
+    if (!out)
+        return fail(XR_ERR_NULL, "out is NULL");
+    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+        return fail(XR_ERR_ARG, "filter = %d unknown", filter);
+    if (elem_size(dtype) == 0)
+        return fail(XR_ERR_DTYPE, "dtype = %d unknown", dtype);
+    if (channels != 1 && channels != 4)
+        return fail(XR_ERR_CHANNELS, "channels = %d", channels);
+    if (in_w < 1 || in_h < 1 || out_w < 1 || out_h < 1)
+        return fail(XR_ERR_SHAPE, "sizes must be positive");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find(tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h));
+    *out = it != g_tuned.end() ? it->second : default_tile(channels);
+    return XR_OK;
+}
+
+int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
+                int32_t out_w, int32_t out_h, const xr_tile *tile)
+{
+    if (!tile)
+        return fail(XR_ERR_NULL, "tile is NULL");
+    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+        return fail(XR_ERR_ARG, "filter = %d unknown", filter);
+    if (elem_size(dtype) == 0)
+        return fail(XR_ERR_DTYPE, "dtype = %d unknown", dtype);
+    if (channels != 1 && channels != 4)
+        return fail(XR_ERR_CHANNELS, "channels = %d", channels);
+    if (in_w < 1 || in_h < 1 || out_w < 1 || out_h < 1)
+        return fail(XR_ERR_SHAPE, "sizes must be positive");
+    const TuneKey key = tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    if (tile->kernel == XR_KERNEL_AUTO) {
+        g_tuned.erase(key);
+        return XR_OK;
+    }
+    const int rc = check_tile(*tile, dtype, channels);
+    if (rc)
+        return rc;
+    g_tuned[key] = *tile;
+    return XR_OK;
+}
+
+int xr_source_taps(int32_t n_in, int32_t n_out, int32_t x, int32_t *x0, int64_t *t_num,
+                   int64_t *t_den)
+{
+    if (!x0 || !t_num || !t_den)
+        return fail(XR_ERR_NULL, "output pointer is NULL");
+    if (n_in < 1 || n_out < 1 || n_in > XR_MAX_SIDE || n_out > XR_MAX_SIDE)
+        return fail(XR_ERR_SHAPE, "sizes %d -> %d outside 1..%d", n_in, n_out, XR_MAX_SIDE);
+    if (x < 0 || x >= n_out)
+        return fail(XR_ERR_RANGE, "x = %d outside [0, %d)", x, n_out);
+    const int64_t num = (2 * static_cast<int64_t>(x) + 1) * n_in - n_out;
+    const int64_t den = 2 * static_cast<int64_t>(n_out);
+    const int64_t q = floor_div(num, den);
+    *x0 = static_cast<int32_t>(q);
+    *t_num = num - q * den;
+    *t_den = den;
+    return XR_OK;
+}
+
+int xr_needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
+                   int32_t *first, int32_t *last)
+{
+    if (!first || !last)
+        return fail(XR_ERR_NULL, "output pointer is NULL");
+    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+        return fail(XR_ERR_ARG, "filter = %d unknown", filter);
+    if (in_h < 1 || out_h < 1 || in_h > XR_MAX_SIDE || out_h > XR_MAX_SIDE)
+        return fail(XR_ERR_SHAPE, "sizes %d -> %d outside 1..%d", in_h, out_h, XR_MAX_SIDE);
+    if (rows < 1 || row0 < 0 || static_cast<int64_t>(row0) + rows > out_h)
+        return fail(XR_ERR_RANGE, "rows [%d, %d) outside [0, %d)", row0, row0 + rows, out_h);
+    needed_rows(in_h, out_h, row0, rows, filter, first, last);
+    return XR_OK;
+}
+
+int xr_thread_of_pixel(const xr_tile *tile, int32_t px, int32_t py, int32_t *block_x,
+                       int32_t *block_y, int32_t *thread_x, int32_t *thread_y, int32_t *sub_x,
+                       int32_t *sub_y)
+{
+    if (!tile || !block_x || !block_y || !thread_x || !thread_y || !sub_x || !sub_y)
+        return fail(XR_ERR_NULL, "NULL pointer");
+    if (tile->block_w < 1 || tile->block_h < 1 || tile->ppt_x < 1 || tile->ppt_y < 1)
+        return fail(XR_ERR_ARG, "tile fields must be positive");
+    if (px < 0 || py < 0)
+        return fail(XR_ERR_RANGE, "pixel (%d, %d) is negative", px, py);
+    // eq. 6: p = b * b_size + t, with b_size = block * ppt and t = thread * ppt + sub
+    const int32_t tw = tile->block_w * tile->ppt_x;
+    const int32_t th = tile->block_h * tile->ppt_y;
+    *block_x = px / tw;
+    *block_y = py / th;
+    *thread_x = (px % tw) / tile->ppt_x;
+    *thread_y = (py % th) / tile->ppt_y;
+    *sub_x = (px % tw) % tile->ppt_x;
+    *sub_y = (py % th) % tile->ppt_y;
+    return XR_OK;
+}
+
+const char *xr_strerror(int code)
+{
+    switch (code) {
+    case XR_OK:
+        return "success";
+    case XR_ERR_NULL:
+        return "null pointer";
+    case XR_ERR_SHAPE:
+        return "invalid size";
+    case XR_ERR_DTYPE:
+        return "invalid or mismatched dtype";
+    case XR_ERR_CHANNELS:
+        return "invalid or mismatched channel count";
+    case XR_ERR_PITCH:
+        return "invalid pitch or alignment";
+    case XR_ERR_RANGE:
+        return "row band out of range";
+    case XR_ERR_ALIAS:
+        return "source and destination overlap";
+    case XR_ERR_WORKSPACE:
+        return "invalid workspace";
+    case XR_ERR_CAPTURE:
+        return "call not allowed during stream capture";
+    case XR_ERR_HIP:
+        return "HIP runtime error";
+    case XR_ERR_ARG:
+        return "invalid argument";
+    default:
+        return "unknown error code";
+    }
+}
+
+const char *xr_last_error(void) { return g_last_error.c_str(); }
+
+int xr_version(void) { return 100; }
+
+}  // extern "C"

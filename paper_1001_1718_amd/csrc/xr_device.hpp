@@ -1,0 +1,206 @@
+// Device-side building blocks shared by every kernel of the library: the
+// coordinate map, the tap weights, and pixel loads/stores per storage type.
+//
+// Every kernel evaluates an output value in the same float32 order:
+//   h_j = w_x0 * p_j0;  h_j = fma(w_x1, p_j1, h_j); ...   (taps ascending)
+//   v   = w_y0 * h_0;   v   = fma(w_y1, h_1, v);   ...   (rows ascending)
+// and the weights come from the same functions below, compiled with
+// floating-point contraction off, so a pixel's value is a pure function of the
+// image and its coordinates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xr {
+namespace dev {
+
+constexpr int kBilinear = 0;
+constexpr int kBicubic = 1;
+
+template <int FILTER>
+struct Taps {
+    static constexpr int K = (FILTER == kBicubic) ? 4 : 2;  // taps per axis
+    static constexpr int LO = (FILTER == kBicubic) ? -1 : 0;  // first tap relative to x0
+};
+
+// Eqs. 1-4 with half-pixel centres: s = ((2x+1) n_in - n_out) / (2 n_out),
+// x0 = floor(s), t = s - x0. The numerator fits in int32 for sides up to
+// 32768; t is one correctly rounded division of two exact integers.
+__device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out, int32_t &x0,
+                                         float &t)
+{
+    const int32_t num = (2 * x + 1) * n_in - n_out;
+    const int32_t den = 2 * n_out;
+    int32_t q = num / den;
+    int32_t rem = num - q * den;
+    if (rem < 0) {  // C division truncates; step down to the floor
+        q -= 1;
+        rem += den;
+    }
+    x0 = q;
+    t = __fdiv_rn(static_cast<float>(rem), static_cast<float>(den));
+}
+
+// Bilinear weights (1 - t, t) for taps x0, x0+1 (eq. 5).
+// Keys cubic weights for a = -1/2 at taps x0-1 .. x0+2, written as the
+// polynomials K(t+1), K(t), K(1-t), K(2-t) of the Keys kernel.
+template <int FILTER>
+__device__ __forceinline__ void weights(float t, float (&w)[Taps<FILTER>::K])
+{
+    if constexpr (FILTER == kBilinear) {
+        w[0] = 1.0f - t;
+        w[1] = t;
+    } else {
+        w[0] = ((2.0f - t) * t - 1.0f) * t * 0.5f;
+        w[1] = ((3.0f * t - 5.0f) * t * t + 2.0f) * 0.5f;
+        w[2] = ((4.0f - 3.0f * t) * t + 1.0f) * t * 0.5f;
+        w[3] = (t - 1.0f) * t * t * 0.5f;
+    }
+}
+
+__device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+// ---- storage types ------------------------------------------------------
+
+__device__ __forceinline__ float u8_to_f32(uint32_t word, int byte)
+{
+    return static_cast<float>((word >> (8 * byte)) & 0xffu);
+}
+
+// Round half to even, clamp to [0, 255].
+__device__ __forceinline__ uint32_t f32_to_u8(float v)
+{
+    v = __builtin_rintf(v);
+    v = __builtin_fminf(__builtin_fmaxf(v, 0.0f), 255.0f);
+    return static_cast<uint32_t>(v);
+}
+
+template <typename T, int C>
+struct Pix;
+
+template <>
+struct Pix<uint8_t, 1> {
+    static constexpr int kBytes = 1;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[1])
+    {
+        v[0] = static_cast<float>(row[col]);
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[1])
+    {
+        row[col] = static_cast<unsigned char>(f32_to_u8(v[0]));
+    }
+};
+
+template <>
+struct Pix<uint8_t, 4> {
+    static constexpr int kBytes = 4;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[4])
+    {
+        const uint32_t w = *reinterpret_cast<const uint32_t *>(row + 4 * col);
+        v[0] = u8_to_f32(w, 0);
+        v[1] = u8_to_f32(w, 1);
+        v[2] = u8_to_f32(w, 2);
+        v[3] = u8_to_f32(w, 3);
+    }
+    __device__ __forceinline__ static uint32_t pack(const float (&v)[4])
+    {
+        return f32_to_u8(v[0]) | (f32_to_u8(v[1]) << 8) | (f32_to_u8(v[2]) << 16) |
+               (f32_to_u8(v[3]) << 24);
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[4])
+    {
+        *reinterpret_cast<uint32_t *>(row + 4 * col) = pack(v);
+    }
+};
+
+template <>
+struct Pix<_Float16, 1> {
+    static constexpr int kBytes = 2;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[1])
+    {
+        v[0] = static_cast<float>(reinterpret_cast<const _Float16 *>(row)[col]);
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[1])
+    {
+        reinterpret_cast<_Float16 *>(row)[col] = static_cast<_Float16>(v[0]);
+    }
+};
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+
+template <>
+struct Pix<_Float16, 4> {
+    static constexpr int kBytes = 8;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[4])
+    {
+        const half4_t h = *reinterpret_cast<const half4_t *>(row + 8 * col);
+        v[0] = static_cast<float>(h[0]);
+        v[1] = static_cast<float>(h[1]);
+        v[2] = static_cast<float>(h[2]);
+        v[3] = static_cast<float>(h[3]);
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[4])
+    {
+        half4_t h;
+        h[0] = static_cast<_Float16>(v[0]);
+        h[1] = static_cast<_Float16>(v[1]);
+        h[2] = static_cast<_Float16>(v[2]);
+        h[3] = static_cast<_Float16>(v[3]);
+        *reinterpret_cast<half4_t *>(row + 8 * col) = h;
+    }
+};
+
+template <>
+struct Pix<float, 1> {
+    static constexpr int kBytes = 4;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[1])
+    {
+        v[0] = reinterpret_cast<const float *>(row)[col];
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[1])
+    {
+        reinterpret_cast<float *>(row)[col] = v[0];
+    }
+};
+
+template <>
+struct Pix<float, 4> {
+    static constexpr int kBytes = 16;
+    __device__ __forceinline__ static void load(const unsigned char *row, int32_t col, float (&v)[4])
+    {
+        const float4 f = *reinterpret_cast<const float4 *>(row + 16 * col);
+        v[0] = f.x;
+        v[1] = f.y;
+        v[2] = f.z;
+        v[3] = f.w;
+    }
+    __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[4])
+    {
+        *reinterpret_cast<float4 *>(row + 16 * col) = make_float4(v[0], v[1], v[2], v[3]);
+    }
+};
+
+// h = sum_i w[i] * p[i] over one source row, taps ascending (first product is
+// a plain multiply, the rest are fused multiply-adds).
+template <int C>
+__device__ __forceinline__ void fma_first(float (&acc)[C], float w, const float (&p)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        acc[c] = w * p[c];
+}
+
+template <int C>
+__device__ __forceinline__ void fma_next(float (&acc)[C], float w, const float (&p)[C])
+{
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+        acc[c] = __builtin_fmaf(w, p[c], acc[c]);
+}
+
+}  // namespace dev
+}  // namespace xr

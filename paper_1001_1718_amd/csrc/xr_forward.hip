@@ -1,0 +1,557 @@
+// Forward resize kernels for gfx950.
+//
+//  k_gather     one thread per output pixel; a workgroup of block_w x block_h
+//               threads covers a block_w x block_h tile (paper section III.A,
+//               eq. 6). Every tap is read from memory. Kept as the paper's
+//               own tiling, for the tile-shape study and as a reference
+//               launch shape.
+//  k_strip      each thread owns ppt_x adjacent output columns and walks a
+//               strip of ppt_y output rows. The horizontally filtered source
+//               rows (the inner sums of eq. 5) are kept in a ring of K
+//               registers and reused by every output row that needs them, so
+//               a source row is filtered once per strip instead of K times.
+//  k_strip_up2  the same walk specialised for an exact x2 upscale on both
+//               axes: output columns/rows alternate between t = 3/4 and
+//               t = 1/4, a thread's ppt_x columns read one contiguous run of
+//               ppt_x/2 + K source pixels with wide loads, and every source
+//               row produces two output rows.
+//
+// All three evaluate each output with the same float32 operation sequence
+// (xr_device.hpp), so their results are bit-identical.
+#include <hip/hip_runtime.h>
+
+#include "xr_device.hpp"
+#include "xr_internal.h"
+
+namespace xr {
+using namespace dev;
+
+// ---------------------------------------------------------------------------
+// helpers: contiguous runs of pixels
+// ---------------------------------------------------------------------------
+
+template <typename T, int C>
+struct PixRaw {
+    static constexpr int kBytes = Pix<T, C>::kBytes;
+};
+
+// Decode pixel `i` of a byte buffer into floats.
+template <typename T, int C>
+__device__ __forceinline__ void decode(const unsigned char *buf, int i, float (&v)[C])
+{
+    Pix<T, C>::load(buf, i, v);
+}
+
+// Copy `N` contiguous pixels starting at byte address `p` (aligned to ALIGN)
+// into registers.
+template <int BYTES, int ALIGN>
+struct alignas(ALIGN) RawBuf {
+    unsigned char b[BYTES];
+};
+
+template <int BYTES, int ALIGN>
+__device__ __forceinline__ RawBuf<BYTES, ALIGN> load_raw(const unsigned char *p)
+{
+    return *reinterpret_cast<const RawBuf<BYTES, ALIGN> *>(__builtin_assume_aligned(p, ALIGN));
+}
+
+template <int BYTES, int ALIGN>
+__device__ __forceinline__ void store_raw(unsigned char *p, const RawBuf<BYTES, ALIGN> &v)
+{
+    *reinterpret_cast<RawBuf<BYTES, ALIGN> *>(__builtin_assume_aligned(p, ALIGN)) = v;
+}
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// ---------------------------------------------------------------------------
+// k_gather
+// ---------------------------------------------------------------------------
+
+template <int FILTER, typename T, int C>
+__global__ void __launch_bounds__(1024) k_gather(ResizeArgs a)
+{
+    using TP = Taps<FILTER>;
+    constexpr int K = TP::K;
+    const int32_t px = blockIdx.x * blockDim.x + threadIdx.x;  // eq. 6
+    const int32_t py = blockIdx.y * blockDim.y + threadIdx.y;
+    if (px >= a.out_w || py >= a.dst_rows)
+        return;
+    const int32_t plane = blockIdx.z;
+    int32_t x0, y0;
+    float tx, ty;
+    axis_tap(px, a.in_w, a.out_w, x0, tx);
+    axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty);
+    float wx[K], wy[K];
+    weights<FILTER>(tx, wx);
+    weights<FILTER>(ty, wy);
+    int32_t ix[K];
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+        ix[i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
+    const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+    float acc[C];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int32_t r = clampi(y0 + TP::LO + j, 0, a.in_h - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(r) * a.src_pitch;
+        float h[C], p[C];
+        Pix<T, C>::load(row, ix[0], p);
+        fma_first(h, wx[0], p);
+#pragma unroll
+        for (int i = 1; i < K; ++i) {
+            Pix<T, C>::load(row, ix[i], p);
+            fma_next(h, wx[i], p);
+        }
+        if (j == 0)
+            fma_first(acc, wy[0], h);
+        else
+            fma_next(acc, wy[j], h);
+    }
+    unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch +
+                         static_cast<int64_t>(py) * a.dst_pitch;
+    Pix<T, C>::store(dst, px, acc);
+}
+
+// ---------------------------------------------------------------------------
+// k_strip (any scale)
+// ---------------------------------------------------------------------------
+
+template <int FILTER, typename T, int C, int PPX>
+struct StripBody {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+
+    int32_t ix[PPX][K];
+    float wx[PPX][K];
+    float ring[K][PPX][C];
+
+    __device__ __forceinline__ void hrow(const ResizeArgs &a, const unsigned char *src, int32_t r,
+                                         float (&out)[PPX][C])
+    {
+        const int32_t rr = clampi(r, 0, a.in_h - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            float p[C];
+            Pix<T, C>::load(row, ix[c][0], p);
+            fma_first(out[c], wx[c][0], p);
+#pragma unroll
+            for (int i = 1; i < K; ++i) {
+                Pix<T, C>::load(row, ix[c][i], p);
+                fma_next(out[c], wx[c][i], p);
+            }
+        }
+    }
+
+    // Process output rows [r_begin, r_end) (band coordinates) of one plane for
+    // the PPX columns starting at col0.
+    __device__ __forceinline__ void run(const ResizeArgs &a, int32_t plane, int32_t col0,
+                                        int32_t r_begin, int32_t r_end)
+    {
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            const int32_t x = min(col0 + c, a.out_w - 1);
+            int32_t x0;
+            float t;
+            axis_tap(x, a.in_w, a.out_w, x0, t);
+            weights<FILTER>(t, wx[c]);
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                ix[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
+        }
+        const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+        unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
+        const int32_t ncols = min(PPX, a.out_w - col0);
+        int32_t ring_lo = -0x20000000;  // forces a full refill on the first row
+        for (int32_t py = r_begin; py < r_end; ++py) {
+            int32_t y0;
+            float ty;
+            axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty);
+            float wy[K];
+            weights<FILTER>(ty, wy);
+            const int32_t lo = y0 + TP::LO;
+            if (lo - ring_lo >= K) {
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    hrow(a, src, lo + j, ring[j]);
+                ring_lo = lo;
+            } else {
+                while (ring_lo < lo) {
+#pragma unroll
+                    for (int j = 0; j + 1 < K; ++j)
+#pragma unroll
+                        for (int c = 0; c < PPX; ++c)
+#pragma unroll
+                            for (int ch = 0; ch < C; ++ch)
+                                ring[j][c][ch] = ring[j + 1][c][ch];
+                    hrow(a, src, ring_lo + K, ring[K - 1]);
+                    ++ring_lo;
+                }
+            }
+            unsigned char *drow = dst + static_cast<int64_t>(py) * a.dst_pitch;
+#pragma unroll
+            for (int c = 0; c < PPX; ++c) {
+                float v[C];
+                fma_first(v, wy[0], ring[0][c]);
+#pragma unroll
+                for (int j = 1; j < K; ++j)
+                    fma_next(v, wy[j], ring[j][c]);
+                if (c < ncols)
+                    Pix<T, C>::store(drow, col0 + c, v);
+            }
+        }
+    }
+};
+
+// Row strip of a thread: threadIdx.y selects one of blockDim.y strips stacked
+// vertically in the tile. blockDim.x is a multiple of the wavefront size, so
+// the strip is uniform across a wavefront.
+__device__ __forceinline__ int32_t strip_begin(int32_t strip_h)
+{
+    return __builtin_amdgcn_readfirstlane((blockIdx.y * blockDim.y + threadIdx.y) * strip_h);
+}
+
+template <int FILTER, typename T, int C, int PPX>
+__global__ void __launch_bounds__(256) k_strip(ResizeArgs a, int32_t strip_h)
+{
+    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(strip_h);
+    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+        return;
+    const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
+    StripBody<FILTER, T, C, PPX> body;
+    body.run(a, blockIdx.z, col0, r_begin, r_end);
+}
+
+// ---------------------------------------------------------------------------
+// k_strip_up2 (exact x2 upscale on both axes)
+// ---------------------------------------------------------------------------
+
+template <int FILTER, typename T, int C, int PPX>
+__global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h)
+{
+    using TP = Taps<FILTER>;
+    constexpr int K = TP::K;
+    constexpr int M = PPX / 2;           // source columns owned per thread
+    constexpr int SPAN = M + K;          // source columns read per row
+    constexpr int PB = Pix<T, C>::kBytes;
+    // byte offset of the run start is (M*thread - K/2) * PB, plus a 16-byte
+    // aligned base when the caller's buffers allow it
+    constexpr int RUN_ALIGN = cmin(16, cgcd(M * PB, (K / 2) * PB));
+    constexpr int OUT_ALIGN = cmin(16, PPX * PB);
+
+    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(strip_h);
+    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+        return;
+    const int32_t k0 = col0 / 2;
+    const int32_t run0 = k0 - K / 2;
+    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
+    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
+    const int32_t plane = blockIdx.z;
+
+    // t = 3/4 on even outputs, 1/4 on odd outputs (s(x) = (2x - 1)/4)
+    float we[K], wo[K];
+    weights<FILTER>(0.75f, we);
+    weights<FILTER>(0.25f, wo);
+
+    const bool interior = run0 >= 0 && run0 + SPAN <= a.in_w && col0 + PPX <= a.out_w;
+    const bool wide = interior && a.aligned16;
+    int32_t sx[SPAN];
+#pragma unroll
+    for (int s = 0; s < SPAN; ++s)
+        sx[s] = clampi(run0 + s, 0, a.in_w - 1);
+
+    const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+    unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
+
+    // source row r -> horizontally filtered values of the PPX output columns
+    auto hrow = [&](int32_t r, float (&out)[PPX][C]) {
+        const int32_t rr = clampi(r, 0, a.in_h - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
+        float p[SPAN][C];
+        if (wide) {
+            const auto raw = load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
+#pragma unroll
+            for (int s = 0; s < SPAN; ++s)
+                decode<T, C>(raw.b, s, p[s]);
+        } else {
+#pragma unroll
+            for (int s = 0; s < SPAN; ++s)
+                Pix<T, C>::load(row, sx[s], p[s]);
+        }
+#pragma unroll
+        for (int q = 0; q < M; ++q) {
+            fma_first(out[2 * q], we[0], p[q]);
+#pragma unroll
+            for (int i = 1; i < K; ++i)
+                fma_next(out[2 * q], we[i], p[q + i]);
+            fma_first(out[2 * q + 1], wo[0], p[q + 1]);
+#pragma unroll
+            for (int i = 1; i < K; ++i)
+                fma_next(out[2 * q + 1], wo[i], p[q + 1 + i]);
+        }
+    };
+
+    const int32_t ncols = min(PPX, a.out_w - col0);
+    auto emit = [&](int32_t y, const float (&w)[K], const float (&ring)[K][PPX][C]) {
+        unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
+        float v[PPX][C];
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            fma_first(v[c], w[0], ring[0][c]);
+#pragma unroll
+            for (int j = 1; j < K; ++j)
+                fma_next(v[c], w[j], ring[j][c]);
+        }
+        if (wide) {
+            RawBuf<PPX * PB, OUT_ALIGN> out;
+#pragma unroll
+            for (int c = 0; c < PPX; ++c)
+                Pix<T, C>::store(out.b, c, v[c]);
+            store_raw<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
+        } else {
+#pragma unroll
+            for (int c = 0; c < PPX; ++c)
+                if (c < ncols)
+                    Pix<T, C>::store(drow, col0 + c, v[c]);
+        }
+    };
+
+    // After filtering source row r the ring holds rows r-K+1 .. r, which are
+    // exactly the taps of output rows 2r-K+1 (odd, t = 1/4) and 2r-K+2 (even,
+    // t = 3/4).
+    const int32_t r_min = (y_b + K - 2 + 1) >> 1;   // ceil((y_b + K - 2) / 2), y_b >= 0
+    const int32_t r_max = (y_e - 1 + K - 1) >> 1;   // floor((y_e - 1 + K - 1) / 2)
+    float ring[K][PPX][C];
+#pragma unroll
+    for (int j = 0; j + 1 < K; ++j)
+        hrow(r_min - K + 1 + j, ring[j + 1]);
+#pragma unroll 4
+    for (int32_t r = r_min; r <= r_max; ++r) {
+#pragma unroll
+        for (int j = 0; j + 1 < K; ++j)
+#pragma unroll
+            for (int c = 0; c < PPX; ++c)
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    ring[j][c][ch] = ring[j + 1][c][ch];
+        hrow(r, ring[K - 1]);
+        const int32_t y_odd = 2 * r - K + 1;
+        const int32_t y_even = y_odd + 1;
+        if (y_odd >= y_b && y_odd < y_e)
+            emit(y_odd, wo, ring);
+        if (y_even >= y_b && y_even < y_e)
+            emit(y_even, we, ring);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// k_batched: one persistent launch over every tile of every job
+// ---------------------------------------------------------------------------
+//
+// Workgroups take tiles from a global ticket counter (jobs are ordered largest
+// first, so the long tiles start early and short ones fill the tail). A tile
+// is a (blockDim.x * kBatchPpx) x (blockDim.y * strip_h) block of one plane
+// of one job; filter and channel count are uniform per tile, so the branch
+// to the right strip body is uniform. The last workgroup to finish resets the
+// counters, so the launch can be replayed (e.g. from a HIP graph) without any
+// host-side clearing.
+
+template <typename T, int FILTER, int C>
+__device__ __forceinline__ void batched_tile(const ResizeArgs &a, int32_t plane, int32_t col0,
+                                             int32_t r_begin, int32_t r_end)
+{
+    StripBody<FILTER, T, C, kBatchPpx> body;
+    body.run(a, plane, col0, r_begin, r_end);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_batched(unsigned char *ws)
+{
+    BatchHeader *hdr = reinterpret_cast<BatchHeader *>(ws);
+    const BatchJob *jobs = reinterpret_cast<const BatchJob *>(ws + kBatchHeaderBytes);
+    const int64_t total = hdr->total_tiles;
+    const int32_t n_jobs = hdr->n_jobs;
+    const int32_t strip_h = hdr->ppt_y;
+    __shared__ uint32_t s_tile;
+    const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
+    for (;;) {
+        if (leader)
+            s_tile = atomicAdd(&hdr->ticket, 1u);
+        __syncthreads();
+        const int64_t tile = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(s_tile));
+        __syncthreads();
+        if (tile >= total)
+            break;
+        int32_t lo = 0, hi = n_jobs - 1;  // last job whose tile_begin <= tile
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= tile)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchJob &job = jobs[lo];
+        const ResizeArgs a = job.a;
+        const int64_t local = tile - job.tile_begin;
+        const int64_t per_plane = static_cast<int64_t>(job.tiles_x) * job.tiles_y;
+        const int32_t plane = static_cast<int32_t>(local / per_plane);
+        const int32_t rem = static_cast<int32_t>(local - plane * per_plane);
+        const int32_t ty = rem / job.tiles_x;
+        const int32_t tx = rem - ty * job.tiles_x;
+        const int32_t col0 = (tx * blockDim.x + threadIdx.x) * kBatchPpx;
+        const int32_t r_begin =
+            __builtin_amdgcn_readfirstlane((ty * blockDim.y + threadIdx.y) * strip_h);
+        if (col0 < a.out_w && r_begin < a.dst_rows) {
+            const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
+            const int32_t kind = job.filter * 2 + (job.channels == 4 ? 1 : 0);
+            switch (kind) {
+            case 0:
+                batched_tile<T, kBilinear, 1>(a, plane, col0, r_begin, r_end);
+                break;
+            case 1:
+                batched_tile<T, kBilinear, 4>(a, plane, col0, r_begin, r_end);
+                break;
+            case 2:
+                batched_tile<T, kBicubic, 1>(a, plane, col0, r_begin, r_end);
+                break;
+            default:
+                batched_tile<T, kBicubic, 4>(a, plane, col0, r_begin, r_end);
+                break;
+            }
+        }
+    }
+    if (leader) {
+        __threadfence();
+        if (atomicAdd(&hdr->done, 1u) == gridDim.x - 1) {
+            atomicExch(&hdr->ticket, 0u);
+            atomicExch(&hdr->done, 0u);
+        }
+    }
+}
+
+hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h,
+                          int32_t grid, hipStream_t stream)
+{
+    unsigned char *p = const_cast<unsigned char *>(static_cast<const unsigned char *>(ws));
+    const dim3 block(block_w, block_h, 1);
+    switch (dtype) {
+    case XR_U8:
+        hipLaunchKernelGGL(k_batched<uint8_t>, dim3(grid), block, 0, stream, p);
+        break;
+    case XR_F16:
+        hipLaunchKernelGGL(k_batched<_Float16>, dim3(grid), block, 0, stream, p);
+        break;
+    default:
+        hipLaunchKernelGGL(k_batched<float>, dim3(grid), block, 0, stream, p);
+        break;
+    }
+    return hipGetLastError();
+}
+
+int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads)
+{
+    int n = 0;
+    hipError_t e;
+    switch (dtype) {
+    case XR_U8:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<uint8_t>, threads, 0);
+        break;
+    case XR_F16:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<_Float16>, threads, 0);
+        break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float>, threads, 0);
+        break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+// ---------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------
+
+bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
+{
+    (void)dtype;
+    if (channels == 4)
+        return ppx == 2 || ppx == 4;
+    return ppx == 4 || ppx == 8;
+}
+
+namespace {
+
+template <int FILTER, typename T, int C>
+hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, hipStream_t stream)
+{
+    if (tile.kernel == XR_KERNEL_GATHER) {
+        const dim3 block(tile.block_w, tile.block_h, 1);
+        const dim3 grid((a.out_w + tile.block_w - 1) / tile.block_w,
+                        (a.dst_rows + tile.block_h - 1) / tile.block_h, a.planes);
+        hipLaunchKernelGGL((k_gather<FILTER, T, C>), grid, block, 0, stream, a);
+        return hipGetLastError();
+    }
+    const int32_t cols_per_block = tile.block_w * tile.ppt_x;
+    const int32_t rows_per_block = tile.block_h * tile.ppt_y;
+    const dim3 block(tile.block_w, tile.block_h, 1);
+    const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
+                    (a.dst_rows + rows_per_block - 1) / rows_per_block, a.planes);
+#define XR_STRIP_CASE(P)                                                                   \
+    case P:                                                                                \
+        if (mode == kUp2)                                                                  \
+            hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,  \
+                               tile.ppt_y);                                                \
+        else                                                                               \
+            hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a,      \
+                               tile.ppt_y);                                                \
+        return hipGetLastError();
+    if constexpr (C == 4) {
+        switch (tile.ppt_x) {
+            XR_STRIP_CASE(2)
+            XR_STRIP_CASE(4)
+        default:
+            return hipErrorInvalidValue;
+        }
+    } else {
+        switch (tile.ppt_x) {
+            XR_STRIP_CASE(4)
+            XR_STRIP_CASE(8)
+        default:
+            return hipErrorInvalidValue;
+        }
+    }
+#undef XR_STRIP_CASE
+}
+
+template <int FILTER>
+hipError_t launch_filter(const ResizeArgs &a, int32_t dtype, int32_t channels, const xr_tile &tile,
+                         int32_t mode, hipStream_t stream)
+{
+    switch (dtype) {
+    case XR_U8:
+        return channels == 4 ? launch_typed<FILTER, uint8_t, 4>(a, tile, mode, stream)
+                             : launch_typed<FILTER, uint8_t, 1>(a, tile, mode, stream);
+    case XR_F16:
+        return channels == 4 ? launch_typed<FILTER, _Float16, 4>(a, tile, mode, stream)
+                             : launch_typed<FILTER, _Float16, 1>(a, tile, mode, stream);
+    case XR_F32:
+        return channels == 4 ? launch_typed<FILTER, float, 4>(a, tile, mode, stream)
+                             : launch_typed<FILTER, float, 1>(a, tile, mode, stream);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
+                          const xr_tile &tile, int32_t mode, hipStream_t stream)
+{
+    if (filter == XR_BICUBIC)
+        return launch_filter<kBicubic>(a, dtype, channels, tile, mode, stream);
+    return launch_filter<kBilinear>(a, dtype, channels, tile, mode, stream);
+}
+
+}  // namespace xr

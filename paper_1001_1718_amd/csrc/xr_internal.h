@@ -1,0 +1,69 @@
+// Internal interface between the C-ABI layer (xr_api.cpp) and the kernels
+// (xr_kernels.hip). Not installed; callers use include/xresize.h.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include "../../include/xresize.h"
+
+namespace xr {
+
+// One resize job, resolved to byte addresses and validated on the host.
+// `src` / `dst` point at the first stored row of plane 0.
+struct ResizeArgs {
+    const unsigned char *src;
+    unsigned char *dst;
+    int64_t src_pitch, src_plane_pitch;
+    int64_t dst_pitch, dst_plane_pitch;
+    int32_t in_w, in_h;      // full logical source size
+    int32_t out_w, out_h;    // full logical destination size
+    int32_t src_row0;        // logical row stored first in src
+    int32_t dst_row0;        // first logical output row to compute
+    int32_t dst_rows;        // number of output rows to compute
+    int32_t planes;
+    int32_t aligned16;       // src, dst and pitches are 16-byte aligned
+};
+
+// Entry of the device job table of the batched launch.
+struct BatchJob {
+    ResizeArgs a;
+    int32_t filter;
+    int32_t channels;
+    int32_t tiles_x;         // tiles per row of the output (per plane)
+    int32_t tiles_y;         // tiles per column of the output (per plane)
+    int64_t tile_begin;      // prefix sum of tiles of the jobs before this one
+};
+
+// Header of the batched workspace; jobs follow at offset kBatchHeaderBytes.
+struct BatchHeader {
+    int64_t total_tiles;
+    int32_t n_jobs;
+    int32_t dtype;
+    int32_t block_w;         // threads per workgroup along x
+    int32_t block_h;         // thread rows per workgroup
+    int32_t ppt_y;           // rows per thread strip
+    int32_t grid;            // workgroups of the persistent launch
+    uint32_t ticket;         // next tile to hand out (self-resetting)
+    uint32_t done;           // workgroups that have finished (self-resetting)
+};
+constexpr size_t kBatchHeaderBytes = 256;
+
+// Shape of an axis that a kernel can specialise on.
+enum AxisMode : int32_t { kGeneral = 0, kUp2 = 1 };
+
+hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
+                          const xr_tile &tile, int32_t mode, hipStream_t stream);
+hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h,
+                          int32_t grid, hipStream_t stream);
+// Workgroups of the batched kernel that fit on one compute unit.
+int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads);
+hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels,
+                           hipStream_t stream);
+
+// Pixels per thread along x that the strip kernel is instantiated for.
+bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx);
+// Output columns per thread of the batched kernel (both channel counts).
+constexpr int32_t kBatchPpx = 4;
+
+}  // namespace xr

@@ -9,8 +9,10 @@ from .fields import (  # noqa: F401
     BatchJob,
     batch_jobs,
     field_u8,
+    field_u8_torch,
     field_unit,
     normal_f32,
     smooth_field,
+    smooth_field_torch,
     uniform_u8,
 )

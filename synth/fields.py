@@ -121,3 +121,43 @@ def batch_jobs(seed: int, count: int = 256, side_lo: int = 64, side_hi: int = 20
         jobs.append(BatchJob(int(h[k]), int(w[k]), oh, ow, int(ch[k]), int(filt[k]),
                              int(seed) * 100000 + k))
     return jobs
+
+
+def smooth_field_torch(height: int, width: int, channels: int, seed: int, device="cuda"):
+    """The smooth field evaluated on ``device`` (torch, float64), shape (H, W, C).
+
+    Same parameter draws as ``smooth_field`` (numpy PCG64, seed + 16 c); the
+    noise comes from a torch generator seeded with the same number, so the
+    values are a stand-in of the same distribution, not bitwise the numpy ones.
+    For large batches whose generation on the host would dominate a run.
+    """
+    import torch
+
+    h, w = int(height), int(width)
+    xs = torch.arange(w, dtype=torch.float64, device=device) / w
+    ys = torch.arange(h, dtype=torch.float64, device=device) / h
+    out = torch.empty((h, w, channels), dtype=torch.float64, device=device)
+    gen = torch.Generator(device=device)
+    for c in range(channels):
+        rng = _rng(seed + 16 * c)
+        f = rng.uniform(-32.0, 32.0, 8)
+        g = rng.uniform(-32.0, 32.0, 8)
+        phi = rng.uniform(0.0, 2.0 * math.pi, 8)
+        acc = torch.full((h, w), 127.5, dtype=torch.float64, device=device)
+        for k in range(8):
+            a = 2.0 * math.pi * float(f[k]) * xs + float(phi[k])
+            b = 2.0 * math.pi * float(g[k]) * ys
+            acc += torch.outer(14.0 * torch.cos(b), torch.sin(a))
+            acc += torch.outer(14.0 * torch.sin(b), torch.cos(a))
+        gen.manual_seed(int(seed) * 7919 + c)
+        acc += 2.0 * torch.randn((h, w), generator=gen, dtype=torch.float64, device=device)
+        out[:, :, c] = acc
+    return out
+
+
+def field_u8_torch(height: int, width: int, channels: int, seed: int, device="cuda"):
+    """``smooth_field_torch`` quantised to uint8 (clip(rint(S), 0, 255))."""
+    import torch
+
+    s = smooth_field_torch(height, width, channels, seed, device)
+    return torch.clamp(torch.round(s), 0.0, 255.0).to(torch.uint8)

@@ -1,0 +1,101 @@
+"""Shared helpers of the GPU parity tests: comparison rules against the oracle.
+
+Tolerances (derived in the design doc from the float32 evaluation order):
+* uint8, dyadic scale ratios (every weight k / 2^m): the float32 sums are exact,
+  so the GPU must equal rint-half-even + clamp of the float64 oracle on every
+  pixel, rounding ties included;
+* uint8, other ratios: a pixel may differ from the oracle's rounding only by
+  one, only where the float64 value lies within U8_EPS of a .5 boundary (there
+  both roundings are within float32 error of the exact value), and on at most
+  max(16, U8_MAX_FLIP_SHARE * size) values (a guard against systematic bias);
+* float16: |gpu - oracle| <= 1e-3 (values in [0, 1]) and at most one float16
+  ulp away from the oracle's own float16 rounding;
+* float32: |gpu - oracle| <= 1e-5 * sum |w_y w_x v| per pixel.
+"""
+
+import numpy as np
+
+from oracle import ref_resize as R
+
+U8_EPS = 2.0 ** -10
+U8_MAX_FLIP_SHARE = 1e-4
+F16_MAX_ABS = 1e-3
+F32_REL = 1e-5
+
+
+def is_dyadic_ratio(n_in: int, n_out: int) -> bool:
+    """True when every offset t of the axis is a multiple of 1/4.
+
+    Then the bilinear weights are multiples of 1/4 and the Keys weights
+    multiples of 1/128, and every float32 partial sum over uint8 pixels is an
+    exact multiple of 2^-14 below 2^23: the GPU's float32 value equals the
+    exact one, so its rounding must match the oracle's everywhere.
+    """
+    x = np.arange(n_out, dtype=np.int64)
+    rem = ((2 * x + 1) * n_in - n_out) % (2 * n_out)
+    return bool(np.all((4 * rem) % (2 * n_out) == 0))
+
+
+def check_u8(gpu: np.ndarray, ref: np.ndarray, exact: bool, what: str = ""):
+    want = R.quantize_u8(ref)
+    gpu = np.asarray(gpu)
+    assert gpu.shape == want.shape, (gpu.shape, want.shape)
+    if exact:
+        bad = np.argwhere(gpu != want)
+        assert bad.size == 0, (f"{what}: {len(bad)} u8 mismatches on a dyadic ratio, first at "
+                               f"{bad[:3].tolist()}: gpu {gpu[tuple(bad[0])]} want {want[tuple(bad[0])]} "
+                               f"ref {ref[tuple(bad[0])]!r}")
+        return 0
+    diff = gpu.astype(np.int32) - want.astype(np.int32)
+    bad = diff != 0
+    n_bad = int(bad.sum())
+    if n_bad:
+        frac = np.abs(ref[bad] - np.floor(ref[bad]) - 0.5)
+        assert np.all(np.abs(diff[bad]) == 1), f"{what}: u8 mismatch larger than 1"
+        assert np.all(frac <= U8_EPS), f"{what}: u8 mismatch away from a .5 boundary (max {frac.max()})"
+        assert n_bad <= max(16, U8_MAX_FLIP_SHARE * gpu.size), f"{what}: {n_bad} u8 flips"
+    return n_bad
+
+
+def check_f16(gpu: np.ndarray, ref: np.ndarray, what: str = ""):
+    g = np.asarray(gpu).astype(np.float64)
+    err = np.abs(g - ref)
+    assert err.max() <= F16_MAX_ABS, f"{what}: float16 max abs error {err.max()}"
+    want = R.quantize_f16(ref).astype(np.float64)
+    ulp = np.spacing(np.abs(want).astype(np.float16)).astype(np.float64)
+    assert np.all(np.abs(g - want) <= ulp + 1e-30), f"{what}: more than one float16 ulp from the oracle"
+    return float(err.max())
+
+
+def check_f32(gpu: np.ndarray, ref: np.ndarray, scale: np.ndarray, what: str = ""):
+    g = np.asarray(gpu).astype(np.float64)
+    err = np.abs(g - ref)
+    lim = F32_REL * scale + 1e-30
+    worst = float((err / lim).max())
+    assert worst <= 1.0, f"{what}: float32 error {worst:.3g} x the 1e-5 * sum|w v| bound"
+    return worst
+
+
+def compare(gpu: np.ndarray, src_np: np.ndarray, out_h: int, out_w: int, filt: int, rows=None,
+            what: str = "", use_c: bool = True):
+    """Compare GPU output rows (P, R, W, C) with the oracle on the same rows."""
+    from oracle import ref_c
+
+    planes = src_np if src_np.ndim == 4 else (src_np[None] if src_np.ndim == 3 else src_np[None, :, :, None])
+    in_h, in_w = planes.shape[1], planes.shape[2]
+    if rows is None:
+        rows = np.arange(out_h)
+    gpu = np.asarray(gpu)
+    if gpu.ndim == 2:
+        gpu = gpu[None, :, :, None]
+    elif gpu.ndim == 3:
+        gpu = gpu[None]
+    ref = (ref_c.resize_rows(planes, out_h, out_w, rows, filt) if use_c
+           else R.resize_rows(planes, out_h, out_w, rows, filt))
+    if planes.dtype == np.uint8:
+        exact = is_dyadic_ratio(in_w, out_w) and is_dyadic_ratio(in_h, out_h)
+        return check_u8(gpu, ref, exact, what)
+    if planes.dtype == np.float16:
+        return check_f16(gpu, ref, what)
+    scale = R.resize_rows(planes, out_h, out_w, rows, filt, absolute=True)
+    return check_f32(gpu, ref, scale, what)

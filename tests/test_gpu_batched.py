@@ -1,0 +1,138 @@
+"""GPU tests of the persistent batched launch (xr_batch_prepare / xr_resize_batched).
+
+* a batch of uneven uint8 jobs (1 and 4 channels, both filters, scales
+  0.25 .. 4): every output bitwise equal to the per-image launch, and within
+  the uint8 rule of the FP64 oracle on sampled rows;
+* replays from a captured HIP graph, with eager work in between, equal the
+  eager result every time (the ticket counter resets itself);
+* the full 256-job batch: bitwise equal to 256 per-image launches;
+* host-side validation of prepare (capture, workspace, dtype mix).
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1001_1718_amd as xr  # noqa: E402
+from gpu_util import compare  # noqa: E402
+from synth import fields  # noqa: E402
+
+DEV = "cuda:0"
+NAMES = {0: "bilinear", 1: "bicubic"}
+
+
+def _make_batch(seed, count, side_hi, content="uniform"):
+    jobs = fields.batch_jobs(seed, count=count, side_hi=side_hi)
+    pairs, srcs = [], []
+    for j in jobs:
+        if content == "uniform":
+            s = torch.from_numpy(fields.uniform_u8((j.in_h, j.in_w, j.channels), j.content_seed)).to(DEV)
+        else:
+            s = fields.field_u8_torch(j.in_h, j.in_w, j.channels, j.content_seed, DEV)
+        d = torch.empty((j.out_h, j.out_w, j.channels), dtype=torch.uint8, device=DEV)
+        pairs.append((s, d, j.filter))
+        srcs.append(s)
+    return jobs, pairs
+
+
+def _per_image(pairs):
+    outs = []
+    for s, d, f in pairs:
+        o = torch.empty_like(d)
+        xr.resize_into(s, o, f)
+        outs.append(o)
+    torch.cuda.synchronize()
+    return outs
+
+
+def test_small_batch_matches_per_image_and_oracle():
+    jobs, pairs = _make_batch(seed=11, count=24, side_hi=300)
+    ref = _per_image(pairs)
+    b = xr.Batch(pairs)
+    b.run()
+    torch.cuda.synchronize()
+    for k, ((s, d, f), r) in enumerate(zip(pairs, ref)):
+        assert torch.equal(d, r), f"job {k}: batched output differs from the per-image launch"
+    rng = np.random.default_rng(1)
+    for k, (j, (s, d, f)) in enumerate(zip(jobs, pairs)):
+        rows = np.unique(np.concatenate([[0, j.out_h - 1], rng.integers(0, j.out_h, 3)]))
+        got = d[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+        compare(got[None], s.cpu().numpy(), j.out_h, j.out_w, f, rows=rows, what=f"job {k}")
+
+
+def test_batch_replays_and_graph():
+    jobs, pairs = _make_batch(seed=12, count=16, side_hi=400)
+    ref = _per_image(pairs)
+    b = xr.Batch(pairs)
+    stream = torch.cuda.Stream()
+    # eager replays: the ticket counter must come back to zero after every launch
+    for _ in range(3):
+        for _, d, _ in pairs:
+            d.zero_()
+        b.run()
+        torch.cuda.synchronize()
+        for (_, d, _), r in zip(pairs, ref):
+            assert torch.equal(d, r)
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            b.run(stream=stream)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for _, d, _ in pairs:
+            d.fill_(7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for k, ((_, d, _), r) in enumerate(zip(pairs, ref)):
+            assert torch.equal(d, r), f"graph replay {rep}: job {k} differs"
+        b.run()  # an eager launch between replays
+        torch.cuda.synchronize()
+
+
+def test_full_batch_bitwise_equal_to_per_image():
+    jobs, pairs = _make_batch(seed=0, count=256, side_hi=2048, content="field")
+    ref = _per_image(pairs)
+    b = xr.Batch(pairs)
+    b.run()
+    torch.cuda.synchronize()
+    bad = [k for k, ((_, d, _), r) in enumerate(zip(pairs, ref)) if not torch.equal(d, r)]
+    assert not bad, f"jobs {bad[:10]} differ between batched and per-image launches"
+    # the oracle on one sampled row of every 8th job
+    rng = np.random.default_rng(2)
+    for k in range(0, 256, 8):
+        j = jobs[k]
+        s, d, f = pairs[k]
+        rows = rng.integers(0, j.out_h, 1)
+        got = d[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+        compare(got[None], s.cpu().numpy(), j.out_h, j.out_w, f, rows=rows, what=f"job {k}")
+
+
+def test_prepare_validation():
+    s = torch.zeros((8, 8, 1), dtype=torch.uint8, device=DEV)
+    d = torch.zeros((16, 16, 1), dtype=torch.uint8, device=DEV)
+    d16 = torch.zeros((16, 16, 1), dtype=torch.float16, device=DEV)
+    s16 = torch.zeros((8, 8, 1), dtype=torch.float16, device=DEV)
+    with pytest.raises(xr.XResizeError) as e:
+        xr.Batch([(s, d, 0), (s16, d16, 1)])  # mixed dtypes
+    assert e.value.code == 3
+    with pytest.raises(xr.XResizeError) as e:
+        xr.Batch([(s, d, 0), (s, d, 1)])  # two jobs write the same output
+    assert e.value.code == 7
+    b = xr.Batch([(s, d, 0)])
+    stream = torch.cuda.Stream()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with pytest.raises(xr.XResizeError) as e:
+            with torch.cuda.graph(graph, stream=stream):
+                xr.Batch([(s, d, 0)], stream=stream)
+    assert e.value.code == 9
+    torch.cuda.synchronize()
+    b.run()
+    torch.cuda.synchronize()

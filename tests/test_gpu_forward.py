@@ -1,0 +1,130 @@
+"""GPU parity of the forward resize against the FP64 oracle (through the C ABI).
+
+Cases: the 512x512 -> 1024x1024 uint8 bilinear workload in full; every dtype x
+channel count x filter x kernel on small ragged images (several tiles plus a
+ragged tail, dyadic and non-dyadic ratios, shrinking, identity, 1-pixel
+sides); bitwise equality of every launch shape; row bands; and the
+4096x4096 RGBA bicubic x2 / x0.5 workload on sampled rows.
+"""
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU only under -m gpu
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1001_1718_amd as xr  # noqa: E402
+from gpu_util import compare  # noqa: E402
+from synth import fields  # noqa: E402
+
+DEV = "cuda:0"
+MODES = {"bilinear": 0, "bicubic": 1}
+
+TILES = {
+    "auto": None,
+    "gather8x8": xr.tile(xr.XR_KERNEL_GATHER, 8, 8),
+    "gather32x4": xr.tile(xr.XR_KERNEL_GATHER, 32, 4),
+    "strip": xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 0, 7),      # ppt_x filled per case
+    "strip_any": xr.tile(xr.XR_KERNEL_STRIP_ANY, 128, 2, 0, 5),
+}
+
+
+def _tile_for(name, channels):
+    t = TILES[name]
+    if t is None or t.kernel == xr.XR_KERNEL_GATHER:
+        return t
+    t = xr.XrTile(*t.as_tuple())
+    t.ppt_x = 4 if channels == 4 else 8
+    return t
+
+
+def _input(dtype, h, w, c, seed):
+    if dtype == np.uint8:
+        return fields.uniform_u8((h, w, c), seed)
+    if dtype == np.float16:
+        return fields.field_unit(h, w, c, seed, np.float16)
+    return fields.normal_f32((h, w, c), seed)
+
+
+def _gpu(src_np, out_h, out_w, mode, tile=None):
+    x = torch.from_numpy(src_np).to(DEV)
+    y = xr.resize(x, (out_h, out_w), mode, tile=tile)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+def test_c1_bilinear_x2_u8_full():
+    img = fields.uniform_u8((512, 512), seed=1001)
+    out = _gpu(img, 1024, 1024, "bilinear")
+    assert compare(out, img, 1024, 1024, 0, what="C1") == 0
+
+
+SHAPES = [
+    ((37, 53), (74, 106)),   # exact x2, ragged
+    ((40, 32), (80, 64)),    # exact x2, aligned
+    ((37, 53), (61, 29)),    # non-dyadic up / down
+    ((64, 96), (32, 48)),    # exact x0.5
+    ((33, 21), (33, 21)),    # identity
+    ((1, 5), (3, 7)),        # one-row source
+    ((9, 1), (20, 2)),       # one-column source
+    ((150, 70), (41, 263)),  # several tiles, mixed
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
+@pytest.mark.parametrize("dtype", [np.uint8, np.float16, np.float32], ids=["u8", "f16", "f32"])
+@pytest.mark.parametrize("channels", [1, 4])
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_small_all_kernels(shape, dtype, channels, mode):
+    (in_h, in_w), (out_h, out_w) = shape
+    img = _input(dtype, in_h, in_w, channels, seed=in_h * 1000 + in_w + channels)
+    outs = {}
+    for name in TILES:
+        outs[name] = _gpu(img, out_h, out_w, mode, _tile_for(name, channels))
+    compare(outs["auto"], img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
+    for name, o in outs.items():
+        np.testing.assert_array_equal(o.view(np.uint8), outs["auto"].view(np.uint8),
+                                      err_msg=f"kernel {name} differs from the default")
+
+
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_bands_match_whole_image(mode):
+    img = fields.field_unit(97, 80, 1, seed=5, dtype=np.float16)[:, :, 0]
+    out_h, out_w = 194, 160
+    whole = _gpu(img, out_h, out_w, mode)
+    x = torch.from_numpy(img).to(DEV)
+    bands = []
+    for row0, rows in [(0, 61), (61, 1), (62, 70), (132, 62)]:
+        first, last = xr.needed_rows(97, out_h, row0, rows, mode)
+        src_band = x[first:last + 1].contiguous()
+        dst_band = torch.empty((rows, out_w), dtype=x.dtype, device=DEV)
+        xr.resize_into(src_band, dst_band, mode, src_row0=first, src_height=97, dst_row0=row0,
+                       dst_height=out_h)
+        bands.append(dst_band)
+    torch.cuda.synchronize()
+    got = torch.cat(bands).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint16), whole.view(np.uint16))
+
+
+def test_band_missing_halo_rejected():
+    x = torch.zeros((10, 8), dtype=torch.uint8, device=DEV)
+    dst = torch.empty((4, 16), dtype=torch.uint8, device=DEV)
+    with pytest.raises(xr.XResizeError) as e:
+        # output rows 8..11 of 40 read source rows 2..7; the band holds rows 4..13
+        xr.resize_into(x, dst, "bicubic", src_row0=4, src_height=20, dst_row0=8, dst_height=40)
+    assert e.value.code == 6
+
+
+@pytest.mark.parametrize("direction", ["up", "down"])
+def test_c2_rgba_u8_bicubic_sampled(direction):
+    img = fields.field_u8(4096, 4096, 4, seed=1002)
+    out = 8192 if direction == "up" else 2048
+    x = torch.from_numpy(img).to(DEV)
+    y = xr.resize(x, (out, out), "bicubic")
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, 1, 2, out - 2, out - 1], rng.integers(0, out, 40)]))
+    got = y[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    assert compare(got[None], img, out, out, 1, rows=rows, what=f"C2 {direction}") == 0
