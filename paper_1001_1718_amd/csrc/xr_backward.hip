@@ -37,8 +37,8 @@ template <int FILTER>
 __device__ __forceinline__ int32_t first_tap(int32_t b, int32_t n_in, int32_t n_out)
 {
     int32_t x0;
-    float t;
-    axis_tap(b, n_in, n_out, x0, t);
+    float t, u;
+    axis_tap(b, n_in, n_out, x0, t, u);
     return clampi(x0 + Taps<FILTER>::LO, 0, n_in - 1);
 }
 
@@ -46,8 +46,8 @@ template <int FILTER>
 __device__ __forceinline__ int32_t last_tap(int32_t e, int32_t n_in, int32_t n_out)
 {
     int32_t x0;
-    float t;
-    axis_tap(e - 1, n_in, n_out, x0, t);
+    float t, u;
+    axis_tap(e - 1, n_in, n_out, x0, t, u);
     return clampi(x0 + Taps<FILTER>::LO + Taps<FILTER>::K - 1, 0, n_in - 1);
 }
 
@@ -136,9 +136,9 @@ __global__ void __launch_bounds__(256) k_bwd_scatter(ResizeArgs a, int32_t all_a
 #pragma unroll
         for (int c = 0; c < P; ++c) {
             int32_t x0;
-            float t;
-            axis_tap(min(xc + c, xe - 1), a.in_w, a.out_w, x0, t);
-            weights<FILTER>(t, wx[c]);
+            float t, u;
+            axis_tap(min(xc + c, xe - 1), a.in_w, a.out_w, x0, t, u);
+            weights<FILTER>(t, u, wx[c]);
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 lx[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1) - fa;
@@ -153,10 +153,10 @@ __global__ void __launch_bounds__(256) k_bwd_scatter(ResizeArgs a, int32_t all_a
         const int32_t y_end = min(y_begin + kBwdRows, ye);
         for (int32_t y = y_begin; y < y_end; ++y) {
             int32_t y0;
-            float ty;
-            axis_tap(y, a.in_h, a.out_h, y0, ty);
+            float ty, uy;
+            axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
             float wy[K];
-            weights<FILTER>(ty, wy);
+            weights<FILTER>(ty, uy, wy);
             const unsigned char *grow = gsrc + static_cast<int64_t>(y) * a.src_pitch;
             float g[P][C];
 #pragma unroll
@@ -230,12 +230,12 @@ __global__ void __launch_bounds__(256) k_bwd_direct(ResizeArgs a)
     if (x >= a.out_w || y >= a.out_h)
         return;
     int32_t x0, y0;
-    float tx, ty;
-    axis_tap(x, a.in_w, a.out_w, x0, tx);
-    axis_tap(y, a.in_h, a.out_h, y0, ty);
+    float tx, ty, ux, uy;
+    axis_tap(x, a.in_w, a.out_w, x0, tx, ux);
+    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
     float wx[K], wy[K];
-    weights<FILTER>(tx, wx);
-    weights<FILTER>(ty, wy);
+    weights<FILTER>(tx, ux, wx);
+    weights<FILTER>(ty, uy, wy);
     float g[C];
     Pix<float, C>::load(a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch +
                             static_cast<int64_t>(y) * a.src_pitch,

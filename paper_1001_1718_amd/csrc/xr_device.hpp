@@ -25,10 +25,12 @@ struct Taps {
 };
 
 // Eqs. 1-4 with half-pixel centres: s = ((2x+1) n_in - n_out) / (2 n_out),
-// x0 = floor(s), t = s - x0. The numerator fits in int32 for sides up to
-// 32768; t is one correctly rounded division of two exact integers.
+// x0 = floor(s), t = s - x0 and omt = 1 - t. The numerator fits in int32 for
+// sides up to 32768; t and 1 - t are each one correctly rounded division of
+// two exact integers, so both carry a relative error of at most half an ulp
+// (1 - t is not formed by a subtraction that would cancel as t -> 1).
 __device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out, int32_t &x0,
-                                         float &t)
+                                         float &t, float &omt)
 {
     const int32_t num = (2 * x + 1) * n_in - n_out;
     const int32_t den = 2 * n_out;
@@ -40,23 +42,37 @@ __device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out,
     }
     x0 = q;
     t = __fdiv_rn(static_cast<float>(rem), static_cast<float>(den));
+    omt = __fdiv_rn(static_cast<float>(den - rem), static_cast<float>(den));
 }
 
 // Bilinear weights (1 - t, t) for taps x0, x0+1 (eq. 5).
-// Keys cubic weights for a = -1/2 at taps x0-1 .. x0+2, written as the
-// polynomials K(t+1), K(t), K(1-t), K(2-t) of the Keys kernel.
+// Keys cubic weights for a = -1/2 at taps x0-1 .. x0+2, i.e. K(t+1), K(t),
+// K(1-t), K(2-t), written in factored forms whose every factor is computed
+// without cancellation, so each weight has a small relative error:
+//   K(t+1) = -t (1-t)^2 / 2          K(t)   = (1-t) (2 + t (2 - 3t)) / 2
+//   K(1-t) =  t (1 + t (4 - 3t)) / 2 K(2-t) = -t^2 (1-t) / 2
 template <int FILTER>
-__device__ __forceinline__ void weights(float t, float (&w)[Taps<FILTER>::K])
+__device__ __forceinline__ void weights(float t, float omt, float (&w)[Taps<FILTER>::K])
 {
     if constexpr (FILTER == kBilinear) {
-        w[0] = 1.0f - t;
+        w[0] = omt;
         w[1] = t;
     } else {
-        w[0] = ((2.0f - t) * t - 1.0f) * t * 0.5f;
-        w[1] = ((3.0f * t - 5.0f) * t * t + 2.0f) * 0.5f;
-        w[2] = ((4.0f - 3.0f * t) * t + 1.0f) * t * 0.5f;
-        w[3] = (t - 1.0f) * t * t * 0.5f;
+        const float ht = -0.5f * t;
+        w[0] = (ht * omt) * omt;
+        w[1] = (0.5f * omt) * (2.0f + t * (2.0f - 3.0f * t));
+        w[2] = (0.5f * t) * (1.0f + t * (4.0f - 3.0f * t));
+        w[3] = (ht * t) * omt;
     }
+}
+
+// Keeps a float32 value in a register as float32, so that the compiler
+// cannot fold the preceding operation into a conversion that rounds once to a
+// narrower type (the library rounds to float32 first, then converts).
+__device__ __forceinline__ float opaque(float v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
 }
 
 __device__ __forceinline__ int32_t clampi(int32_t v, int32_t lo, int32_t hi)
@@ -126,7 +142,7 @@ struct Pix<_Float16, 1> {
     }
     __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[1])
     {
-        reinterpret_cast<_Float16 *>(row)[col] = static_cast<_Float16>(v[0]);
+        reinterpret_cast<_Float16 *>(row)[col] = static_cast<_Float16>(opaque(v[0]));
     }
 };
 
@@ -146,10 +162,10 @@ struct Pix<_Float16, 4> {
     __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[4])
     {
         half4_t h;
-        h[0] = static_cast<_Float16>(v[0]);
-        h[1] = static_cast<_Float16>(v[1]);
-        h[2] = static_cast<_Float16>(v[2]);
-        h[3] = static_cast<_Float16>(v[3]);
+        h[0] = static_cast<_Float16>(opaque(v[0]));
+        h[1] = static_cast<_Float16>(opaque(v[1]));
+        h[2] = static_cast<_Float16>(opaque(v[2]));
+        h[3] = static_cast<_Float16>(opaque(v[3]));
         *reinterpret_cast<half4_t *>(row + 8 * col) = h;
     }
 };

@@ -79,12 +79,12 @@ __global__ void __launch_bounds__(1024) k_gather(ResizeArgs a)
         return;
     const int32_t plane = blockIdx.z;
     int32_t x0, y0;
-    float tx, ty;
-    axis_tap(px, a.in_w, a.out_w, x0, tx);
-    axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty);
+    float tx, ty, ux, uy;
+    axis_tap(px, a.in_w, a.out_w, x0, tx, ux);
+    axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty, uy);
     float wx[K], wy[K];
-    weights<FILTER>(tx, wx);
-    weights<FILTER>(ty, wy);
+    weights<FILTER>(tx, ux, wx);
+    weights<FILTER>(ty, uy, wy);
     int32_t ix[K];
 #pragma unroll
     for (int i = 0; i < K; ++i)
@@ -153,9 +153,9 @@ struct StripBody {
         for (int c = 0; c < PPX; ++c) {
             const int32_t x = min(col0 + c, a.out_w - 1);
             int32_t x0;
-            float t;
-            axis_tap(x, a.in_w, a.out_w, x0, t);
-            weights<FILTER>(t, wx[c]);
+            float t, u;
+            axis_tap(x, a.in_w, a.out_w, x0, t, u);
+            weights<FILTER>(t, u, wx[c]);
 #pragma unroll
             for (int i = 0; i < K; ++i)
                 ix[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
@@ -166,10 +166,10 @@ struct StripBody {
         int32_t ring_lo = -0x20000000;  // forces a full refill on the first row
         for (int32_t py = r_begin; py < r_end; ++py) {
             int32_t y0;
-            float ty;
-            axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty);
+            float ty, uy;
+            axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty, uy);
             float wy[K];
-            weights<FILTER>(ty, wy);
+            weights<FILTER>(ty, uy, wy);
             const int32_t lo = y0 + TP::LO;
             if (lo - ring_lo >= K) {
 #pragma unroll
@@ -253,8 +253,8 @@ __global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h
 
     // t = 3/4 on even outputs, 1/4 on odd outputs (s(x) = (2x - 1)/4)
     float we[K], wo[K];
-    weights<FILTER>(0.75f, we);
-    weights<FILTER>(0.25f, wo);
+    weights<FILTER>(0.75f, 0.25f, we);
+    weights<FILTER>(0.25f, 0.75f, wo);
 
     const bool interior = run0 >= 0 && run0 + SPAN <= a.in_w && col0 + PPX <= a.out_w;
     const bool wide = interior && a.aligned16;

@@ -5,9 +5,10 @@ Tolerances (derived in the design doc from the float32 evaluation order):
   so the GPU must equal rint-half-even + clamp of the float64 oracle on every
   pixel, rounding ties included;
 * uint8, other ratios: a pixel may differ from the oracle's rounding only by
-  one, only where the float64 value lies within U8_EPS of a .5 boundary (there
-  both roundings are within float32 error of the exact value), and on at most
-  max(16, U8_MAX_FLIP_SHARE * size) values (a guard against systematic bias);
+  one, and only where the float64 value lies within U8_EPS of a .5 boundary:
+  there both roundings are within float32 error of the exact value (ratios
+  with exact ties, such as t = 1/3 weights, produce many such pixels; the
+  rounding mode itself is pinned by the dyadic cases, which must be exact);
 * float16: |gpu - oracle| <= 1e-3 (values in [0, 1]) and at most one float16
   ulp away from the oracle's own float16 rounding;
 * float32: |gpu - oracle| <= 1e-5 * sum |w_y w_x v| per pixel.
@@ -18,7 +19,6 @@ import numpy as np
 from oracle import ref_resize as R
 
 U8_EPS = 2.0 ** -10
-U8_MAX_FLIP_SHARE = 1e-4
 F16_MAX_ABS = 1e-3
 F32_REL = 1e-5
 
@@ -53,7 +53,6 @@ def check_u8(gpu: np.ndarray, ref: np.ndarray, exact: bool, what: str = ""):
         frac = np.abs(ref[bad] - np.floor(ref[bad]) - 0.5)
         assert np.all(np.abs(diff[bad]) == 1), f"{what}: u8 mismatch larger than 1"
         assert np.all(frac <= U8_EPS), f"{what}: u8 mismatch away from a .5 boundary (max {frac.max()})"
-        assert n_bad <= max(16, U8_MAX_FLIP_SHARE * gpu.size), f"{what}: {n_bad} u8 flips"
     return n_bad
 
 
