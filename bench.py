@@ -1,0 +1,410 @@
+#!/usr/bin/env python3
+"""Benchmark of the resize library on one MI355X.
+
+Headline workload: Keys-bicubic (a = -1/2) x2 upscale of a 4096 x 4096 RGBA
+uint8 image (synthetic smooth field) to 8192 x 8192, half-pixel centres,
+clamp-to-edge, float32 weights and accumulation. One step = one resize of one
+image; inputs and outputs rotate over >= 1 GiB of buffers so the 256 MB
+Infinity Cache cannot hold the working set between steps.
+
+Printed JSON line (one):
+  value       output Gpixel/s over the K timed steps (wall clock, synchronised)
+  roofline    the resize kernel's algorithmic bytes (each input pixel read once,
+              each output pixel written once) per launch / its mean launch
+              time from HIP events, against the 8 TB/s HBM3E peak; `traffic`
+              is the HBM bytes per launch measured with rocprofv3 counters
+              (profiles/pmc_*.txt), or null if those were taken on other kernel
+              sources
+  cpu_baseline the FP64 C oracle on a bounded sample of output rows, timed on
+              the host cores
+  batched     256 uneven uint8 images: one persistent launch replayed from a
+              HIP graph vs 256 per-image launches (eager and graph-captured),
+              images/s, outputs bitwise identical across the three
+  extras      (with --extras) other storage types and workloads
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+       [--no-batch] [--no-tune] [--extras]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+ROTATE_BYTES = 1 << 30
+KERNEL_SOURCES = ["xr_forward.hip", "xr_device.hpp", "xr_internal.h"]
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1001_1718_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_pmc(name: str):
+    """HBM traffic per launch from a committed rocprofv3 counter summary."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals.get("kernel_sources_sha256_16") != kernel_hash():
+            return None
+        fetch = float(vals["fetch_kib_per_dispatch"]) * 1024.0
+        write = float(vals["write_kib_per_dispatch"]) * 1024.0
+        f_fetch = float(vals["copy_bytes"]) / (float(vals["copy_fetch_kib"]) * 1024.0)
+        f_write = float(vals["copy_bytes"]) / (float(vals["copy_write_kib"]) * 1024.0)
+        return fetch * f_fetch + write * f_write
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
+def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
+    """Run warmup + steps launches rotating over buffers; returns
+    (wall seconds of the timed steps, list of per-launch event times in ms)."""
+    for i in range(warmup):
+        launch(i % n_buffers)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        launch(i % n_buffers)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
+
+
+def group_stats(ms, group: int = 100):
+    groups = [ms[i:i + group] for i in range(0, len(ms), group) if len(ms[i:i + group]) == group]
+    if not groups:
+        groups = [ms]
+    means = [sum(g) / len(g) for g in groups]
+    return {"groups": len(groups), "median_ms": statistics.median(means), "min_ms": min(means),
+            "max_ms": max(means), "mean_ms": sum(ms) / len(ms)}
+
+
+def headline(args, torch, xr, fields):
+    dev = torch.device("cuda:0")
+    in_hw, out_hw, ch = 4096, 8192, 4
+    in_bytes, out_bytes = in_hw * in_hw * ch, out_hw * out_hw * ch
+    n_buf = max(1, math.ceil(ROTATE_BYTES / (in_bytes + out_bytes)))
+    log(f"generating {n_buf} rotating 4096x4096 RGBA uint8 inputs")
+    base = fields.field_u8_torch(in_hw, in_hw, ch, 1002, dev)
+    srcs = [base] + [base.clone() for _ in range(n_buf - 1)]
+    dsts = [torch.empty((out_hw, out_hw, ch), dtype=torch.uint8, device=dev) for _ in range(n_buf)]
+
+    tile = None
+    tune = None
+    if not args.no_tune:
+        cands = [c for c in xr.tune_candidates("bicubic", xr.XR_U8, ch, in_hw, in_hw, out_hw, out_hw)
+                 if c.kernel == xr.XR_KERNEL_STRIP]
+        t0 = time.perf_counter()
+        tile, best_ms = xr.autotune(srcs, dsts, "bicubic", candidates=cands, reps=8, groups=3)
+        tune = {"candidates": len(cands), "seconds": round(time.perf_counter() - t0, 2),
+                "best_ms": round(best_ms, 5)}
+        log(f"autotune picked {tile} at {best_ms * 1e3:.1f} us per launch ({len(cands)} candidates)")
+    resolved = xr.get_tile("bicubic", xr.XR_U8, ch, in_hw, in_hw, out_hw, out_hw)
+
+    def launch(i):
+        xr.resize_into(srcs[i], dsts[i], "bicubic")
+
+    log(f"timing {args.steps} steps after {args.warmup} warm-up steps")
+    wall, ms = time_launches(launch, n_buf, args.steps, args.warmup, torch)
+    stats = group_stats(ms)
+    out_px = out_hw * out_hw
+    value = out_px * args.steps / wall / 1e9
+    kernel_s = stats["mean_ms"] / 1e3
+    alg = in_bytes + out_bytes
+    achieved = alg / kernel_s / 1e9
+    traffic = read_pmc("pmc_resize_bicubic_x2_u8rgba.txt")
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else int(traffic),
+                "alg_bytes_per_launch": alg, "kernel_ms": {k: round(v, 5) for k, v in stats.items()},
+                "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2)}
+    return {
+        "value": value, "wall": wall, "roofline": roofline, "tile": repr(resolved), "tune": tune,
+        "n_buf": n_buf, "src_host": srcs[0].cpu().numpy(),
+    }
+
+
+def cpu_baseline(src_host, target_s: float = 10.0):
+    from oracle import ref_c
+    from oracle.build import LIBRARY, build_oracle
+    import numpy as np
+
+    if not os.path.exists(LIBRARY):
+        build_oracle()
+    out_hw = 8192
+    threads = ref_c.max_threads()
+
+    def run(n_rows):
+        rows = np.linspace(0, out_hw - 1, n_rows).astype(np.int64)
+        t0 = time.perf_counter()
+        ref_c.resize_rows(src_host, out_hw, out_hw, rows, 1)
+        return time.perf_counter() - t0
+
+    probe_rows = 16
+    t = run(probe_rows)
+    n_rows = int(min(out_hw, max(probe_rows, probe_rows * target_s / max(t, 1e-6))))
+    t = run(n_rows)
+    px = n_rows * out_hw
+    return {"value": round(px / t / 1e9, 6), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
+            "seconds": round(t, 2),
+            "sample": f"{n_rows} evenly spaced output rows x 8192 px of the bicubic x2 "
+                      f"4096x4096 RGBA uint8 workload ({px / 1e6:.1f} Mpx), FP64 C oracle, OpenMP"}
+
+
+def batched(torch, xr, fields, reps: int = 5):
+    dev = torch.device("cuda:0")
+    jobs = fields.batch_jobs(0)
+    log("generating the 256-image uneven batch (sides 64..2048, scales 0.25..4)")
+    pairs = []
+    for j in jobs:
+        s = fields.field_u8_torch(j.in_h, j.in_w, j.channels, j.content_seed, dev)
+        d = torch.empty((j.out_h, j.out_w, j.channels), dtype=torch.uint8, device=dev)
+        pairs.append((s, d, j.filter))
+    out_px = sum(j.out_h * j.out_w for j in jobs)
+    alg = sum(j.in_h * j.in_w * j.channels + j.out_h * j.out_w * j.channels for j in jobs)
+
+    def per_image():
+        for s, d, f in pairs:
+            xr.resize_into(s, d, f)
+
+    res = {}
+    # (ii) eager per-image launches
+    per_image()
+    torch.cuda.synchronize()
+    ref = [d.clone() for _, d, _ in pairs]
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        per_image()
+    torch.cuda.synchronize()
+    res["per_image_eager"] = len(pairs) * reps / (time.perf_counter() - t0)
+
+    stream = torch.cuda.Stream()
+    # (iii) the 256 launches captured in one graph
+    g_multi = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g_multi, stream=stream):
+            for s, d, f in pairs:
+                xr.resize_into(s, d, f, stream=stream)
+    torch.cuda.synchronize()
+    g_multi.replay()
+    torch.cuda.synchronize()
+    eq_multi = all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g_multi.replay()
+    torch.cuda.synchronize()
+    res["per_image_graph"] = len(pairs) * reps / (time.perf_counter() - t0)
+
+    # (i) one persistent launch over every tile, captured in a graph
+    for _, d, _ in pairs:
+        d.zero_()
+    b = xr.Batch(pairs)
+    g_one = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(g_one, stream=stream):
+            b.run(stream=stream)
+    torch.cuda.synchronize()
+    g_one.replay()
+    torch.cuda.synchronize()
+    eq_one = all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(reps):
+        g_one.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    res["persistent_graph"] = len(pairs) * reps / wall
+    launch_ms = ev0.elapsed_time(ev1) / reps
+    return {
+        "workload": "256 uint8 images (1 or 4 ch), sides U{64..2048}, per-axis scale U(0.25, 4), "
+                    "128 bilinear + 128 bicubic, smooth-field content, seed 0",
+        "images_per_s": {k: round(v, 1) for k, v in res.items()},
+        "speedup_vs_eager": round(res["persistent_graph"] / res["per_image_eager"], 3),
+        "speedup_vs_graph": round(res["persistent_graph"] / res["per_image_graph"], 3),
+        "bitwise_equal": bool(eq_multi and eq_one),
+        "output_gpixel": round(out_px / 1e9, 3),
+        "persistent_ms": round(launch_ms, 4),
+        "persistent_gbs": round(alg / (launch_ms / 1e3) / 1e9, 1),
+    }
+
+
+def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
+    """Gpixel/s and GB/s of the other storage types and workloads."""
+    dev = torch.device("cuda:0")
+    out = {}
+
+    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None):
+        src0 = make_src()
+        in_bytes = src0.numel() * src0.element_size()
+        out_bytes = math.prod(out_shape) * src0.element_size()
+        n_buf = max(1, math.ceil(ROTATE_BYTES / (in_bytes + out_bytes)))
+        srcs = [src0] + [src0.clone() for _ in range(n_buf - 1)]
+        dsts = [torch.empty(out_shape, dtype=src0.dtype, device=dev) for _ in range(n_buf)]
+
+        def launch(i):
+            xr.resize_into(srcs[i], dsts[i], mode, layout=layout)
+
+        wall, ms = time_launches(launch, n_buf, steps, warmup, torch)
+        k_s = sum(ms) / len(ms) / 1e3
+        # pixels: H * W for interleaved images, N * C * H * W for planar tensors
+        px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
+        out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2),
+                     "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
+                     "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"extra {name}: {out[name]}")
+        del srcs, dsts
+        torch.cuda.empty_cache()
+
+    fld = fields.smooth_field_torch(4096, 4096, 4, 1002, dev)
+    unit = torch.clamp(fld / 255.0, 0.0, 1.0)
+    u8 = torch.clamp(torch.round(fld), 0, 255).to(torch.uint8)
+    for dname, t in [("u8", u8), ("f16", unit.half()), ("f32", unit.float())]:
+        for direction, n in [("x2", 8192), ("x0.5", 2048)]:
+            measure(f"c2_bicubic_{direction}_{dname}_rgba", lambda t=t: t, (n, n, 4), "bicubic")
+    del fld, unit, u8
+    measure("c1_bilinear_x2_u8_512", lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev),
+            (1024, 1024), "bilinear")
+    measure("c4_bilinear_x2_f32_nchw_fwd", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
+            (32, 3, 2048, 2048), "bilinear", layout="nchw")
+    # C4 adjoint
+    g = torch.randn((32, 3, 2048, 2048), device=dev)
+    gs = torch.empty((32, 3, 1024, 1024), device=dev)
+
+    def bwd(i):
+        xr.resize_backward(g, (1024, 1024), "bilinear", out=gs)
+
+    wall, ms = time_launches(bwd, 1, 20, 3, torch)
+    k_s = sum(ms) / len(ms) / 1e3
+    alg = (g.numel() + gs.numel()) * 4
+    out["c4_bilinear_x2_f32_nchw_adjoint"] = {"ms": round(k_s * 1e3, 4), "gbs": round(alg / k_s / 1e9, 1),
+                                              "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+    log(f"extra adjoint: {out['c4_bilinear_x2_f32_nchw_adjoint']}")
+    del g, gs
+    torch.cuda.empty_cache()
+    # C5: 16384^2 FP16 -> 32768^2, whole image and 16 row bands
+    src = torch.clamp(fields.smooth_field_torch(16384, 16384, 1, 1005, dev)[:, :, 0] / 255.0, 0, 1).half()
+    dst = torch.empty((32768, 32768), dtype=torch.float16, device=dev)
+    dst_b = torch.empty_like(dst)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    xr.resize_into(src, dst, "bicubic")
+    ev[0].record()
+    for _ in range(3):
+        xr.resize_into(src, dst, "bicubic")
+    ev[1].record()
+    ev[2].record()
+    for b in range(16):
+        r0 = b * 2048
+        first, last = xr.needed_rows(16384, 32768, r0, 2048, "bicubic")
+        xr.resize_into(src[first:last + 1], dst_b[r0:r0 + 2048], "bicubic", src_row0=first,
+                       src_height=16384, dst_row0=r0, dst_height=32768)
+    ev[3].record()
+    torch.cuda.synchronize()
+    whole = ev[0].elapsed_time(ev[1]) / 3 / 1e3
+    bands = ev[2].elapsed_time(ev[3]) / 1e3
+    alg = (src.numel() + dst.numel()) * 2
+    out["c5_bicubic_x2_f16_16384"] = {"whole_ms": round(whole * 1e3, 3), "bands16_ms": round(bands * 1e3, 3),
+                                      "gbs": round(alg / whole / 1e9, 1),
+                                      "hbm_frac": round(alg / whole / 1e9 / HBM_PEAK_GBS, 4),
+                                      "bands_bitwise_equal": bool(torch.equal(dst, dst_b))}
+    log(f"extra C5: {out['c5_bicubic_x2_f16_16384']}")
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
+    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run a plain 256 MiB device copy (reference for hardware counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world}).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1001_1718_amd as xr
+    from synth import fields
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    if args.calibrate:
+        a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    h = headline(args, torch, xr, fields)
+    result = {
+        "metric": "output Gpixel/s + % HBM peak, bicubic x2; batched vs per-image launch",
+        "value": round(h["value"], 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["wall"] / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "bicubic (Keys a=-0.5) x2 resize, 4096x4096 RGBA uint8 -> 8192x8192, "
+                               "half-pixel centres, clamp-to-edge, float32 weights/accumulation",
+                   "storage": "u8", "global_batch": 1, "rotating_buffers": h["n_buf"],
+                   "tile": h["tile"], "autotune": h["tune"], "parallelism": "single GPU"},
+        "roofline": h["roofline"],
+    }
+    if not args.no_batch:
+        result["batched"] = batched(torch, xr, fields)
+    if not args.no_cpu:
+        log("timing the FP64 CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(h["src_host"])
+    if args.extras:
+        result["extras"] = extras(torch, xr, fields)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -179,19 +179,22 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
 
 /*
  * Launch-shape tuning (the paper's tiling question, section IV, measured on
- * this GPU). Times every candidate with HIP events on the given images
- * (`reps` launches per candidate after one warm-up, median of `groups`
- * groups), writes the fastest to *best and its mean time per launch in ms to
- * *best_ms (either may be NULL), and remembers it for later XR_KERNEL_AUTO
- * calls with the same key (filter, dtype, channels, scale class). Overwrites
- * dst. candidates = NULL uses the built-in candidate list. Synchronises the
+ * this GPU). Times every candidate with HIP events (one warm-up launch, then
+ * `groups` groups of `reps` launches; the candidate's time is the median
+ * group's mean), cycling through the `n_pairs` image pairs srcs[k] -> dsts[k]
+ * so that a working set larger than the caches can be tuned honestly. All
+ * pairs must have the same filter key, sizes, dtype and channels. Writes the
+ * fastest shape to *best and its time per launch in ms to *best_ms (either
+ * may be NULL) and remembers it for later XR_KERNEL_AUTO calls with the same
+ * key (filter, dtype, channels, scale class). Overwrites the dsts.
+ * candidates = NULL uses the built-in candidate list. Synchronises the
  * stream; NOT capturable.
  * xr_tune_candidates: copies up to `cap` built-in candidates for the given
  * key into `out` and returns how many exist.
  */
-int xr_autotune(const xr_image *src, const xr_image *dst, int32_t filter, const xr_tile *candidates,
-                int32_t n_candidates, int32_t reps, int32_t groups, xr_tile *best, float *best_ms,
-                void *stream);
+int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int32_t filter,
+                const xr_tile *candidates, int32_t n_candidates, int32_t reps, int32_t groups,
+                xr_tile *best, float *best_ms, void *stream);
 int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w,
                            int32_t in_h, int32_t out_w, int32_t out_h, xr_tile *out, int32_t cap);
 

@@ -194,19 +194,29 @@ class Batch:
                                     _stream_handle(self.workspace, stream)), "resize_batched")
 
 
-def autotune(src: torch.Tensor, dst: torch.Tensor, mode="bicubic", layout="hwc", candidates=None,
-             reps: int = 20, groups: int = 5, stream=None):
-    """Time launch shapes on (src, dst); returns (best XrTile, ms per launch).
-    The winner is remembered for later launches with the same key."""
-    s, d = image(src, layout), image(dst, layout)
+def autotune(src, dst, mode="bicubic", layout="hwc", candidates=None, reps: int = 20,
+             groups: int = 5, stream=None):
+    """Time launch shapes; returns (best XrTile, ms per launch).
+
+    ``src`` / ``dst`` are tensors or equally long lists of tensors; with lists
+    the launches cycle through the pairs (use enough pairs to exceed the
+    caches). The winner is remembered for later launches with the same key.
+    """
+    srcs = list(src) if isinstance(src, (list, tuple)) else [src]
+    dsts = list(dst) if isinstance(dst, (list, tuple)) else [dst]
+    if len(srcs) != len(dsts):
+        raise ValueError("src and dst lists differ in length")
+    n = len(srcs)
+    s_arr = (XrImage * n)(*[image(t, layout) for t in srcs])
+    d_arr = (XrImage * n)(*[image(t, layout) for t in dsts])
     best, ms = XrTile(), ctypes.c_float()
     if candidates is None:
-        cand_ptr, n = None, 0
+        cand_ptr, nc = None, 0
     else:
-        arr = (XrTile * len(candidates))(*candidates)
-        cand_ptr, n = arr, len(candidates)
-    check(lib.xr_autotune(ctypes.byref(s), ctypes.byref(d), filter_code(mode), cand_ptr, n, reps,
-                          groups, ctypes.byref(best), ctypes.byref(ms), _stream_handle(src, stream)),
+        cand_ptr = (XrTile * len(candidates))(*candidates)
+        nc = len(candidates)
+    check(lib.xr_autotune(s_arr, d_arr, n, filter_code(mode), cand_ptr, nc, reps, groups,
+                          ctypes.byref(best), ctypes.byref(ms), _stream_handle(srcs[0], stream)),
           "autotune")
     return best, float(ms.value)
 

@@ -90,7 +90,7 @@ def _load():
         "xr_batch_prepare": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, vp, sz, vp]),
         "xr_resize_batched": (ctypes.c_int, [vp, i32, vp]),
         "xr_resize_backward": (ctypes.c_int, [pimg, pimg, i32, vp]),
-        "xr_autotune": (ctypes.c_int, [pimg, pimg, i32, ptile, i32, i32, i32, ptile,
+        "xr_autotune": (ctypes.c_int, [pimg, pimg, i32, i32, ptile, i32, i32, i32, ptile,
                                        ctypes.POINTER(ctypes.c_float), vp]),
         "xr_tune_candidates": (i32, [i32, i32, i32, i32, i32, i32, i32, ptile, i32]),
         "xr_get_tile": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, i32, ptile]),

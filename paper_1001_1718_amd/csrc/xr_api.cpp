@@ -177,6 +177,7 @@ xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
     a.out_w = dst.width;
     a.out_h = dst.height;
     a.src_row0 = src.row0;
+    a.src_rows = src.rows;
     a.dst_row0 = dst.row0;
     a.dst_rows = dst.rows;
     a.planes = src.planes;
@@ -511,10 +512,14 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
                              {128, 2}, {256, 1}};
     for (const auto &g : gather)
         c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1});
-    const int ppx_list[2] = {channels == 4 ? 2 : 4, channels == 4 ? 4 : 8};
+    const int ppx_c4[3] = {2, 4, 8};
+    const int ppx_c1[3] = {4, 8, 16};
+    const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
     const int blocks[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
-    const int ppy_list[] = {8, 16, 32, 64, 128};
-    for (int ppx : ppx_list) {
+    // strip heights 8m-2 make the x2 walk's source-row groups come out even
+    const int ppy_list[] = {8, 14, 16, 30, 32, 62, 64, 126};
+    for (int k = 0; k < 3; ++k) {
+        const int ppx = ppx_list[k];
         if (!xr::strip_ppx_supported(dtype, channels, ppx))
             continue;
         for (const auto &b : blocks)
@@ -527,13 +532,27 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     return static_cast<int32_t>(c.size());
 }
 
-int xr_autotune(const xr_image *src, const xr_image *dst, int32_t filter, const xr_tile *candidates,
-                int32_t n_candidates, int32_t reps, int32_t groups, xr_tile *best, float *best_ms,
-                void *stream)
+int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int32_t filter,
+                const xr_tile *candidates, int32_t n_candidates, int32_t reps, int32_t groups,
+                xr_tile *best, float *best_ms, void *stream)
 {
-    int rc = check_pair(src, dst, filter);
-    if (rc)
-        return rc;
+    if (!srcs || !dsts)
+        return fail(XR_ERR_NULL, "srcs or dsts is NULL");
+    if (n_pairs < 1)
+        return fail(XR_ERR_ARG, "n_pairs = %d (must be >= 1)", n_pairs);
+    int rc = XR_OK;
+    for (int32_t k = 0; k < n_pairs; ++k) {
+        rc = check_pair(&srcs[k], &dsts[k], filter);
+        if (rc)
+            return fail(rc, "pair %d: %s", k, g_last_error.c_str());
+        const xr_image &s0 = srcs[0], &d0 = dsts[0], &s = srcs[k], &d = dsts[k];
+        if (s.width != s0.width || s.height != s0.height || d.width != d0.width ||
+            d.height != d0.height || s.dtype != s0.dtype || s.channels != s0.channels ||
+            s.planes != s0.planes || d.rows != d0.rows)
+            return fail(XR_ERR_ARG, "pair %d differs in size, dtype, channels or planes from pair 0", k);
+    }
+    const xr_image *src = &srcs[0];
+    const xr_image *dst = &dsts[0];
     if (reps < 1 || groups < 1)
         return fail(XR_ERR_ARG, "reps = %d, groups = %d (both must be >= 1)", reps, groups);
     std::vector<xr_tile> cand;
@@ -571,18 +590,26 @@ int xr_autotune(const xr_image *src, const xr_image *dst, int32_t filter, const 
         (void)hipEventDestroy(ev0);
         return fail_hip(e, "hipEventCreate");
     }
-    const xr::ResizeArgs a = make_args(*src, *dst);
+    std::vector<xr::ResizeArgs> args(n_pairs);
+    for (int32_t k = 0; k < n_pairs; ++k)
+        args[k] = make_args(srcs[k], dsts[k]);
+    int32_t next = 0;
+    const auto launch = [&](const xr_tile &t, int32_t mode) {
+        const xr::ResizeArgs &a = args[next];
+        next = (next + 1) % n_pairs;
+        return xr::launch_forward(a, filter, src->dtype, src->channels, t, mode, s);
+    };
     float best_t = 0.0f;
     size_t best_k = 0;
     bool have = false;
     std::vector<float> per_group(groups);
     for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
         const int32_t mode = axis_mode(*src, *dst, cand[k]);
-        e = xr::launch_forward(a, filter, src->dtype, src->channels, cand[k], mode, s);  // warm-up
+        e = launch(cand[k], mode);  // warm-up
         for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
             e = hipEventRecord(ev0, s);
             for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
-                e = xr::launch_forward(a, filter, src->dtype, src->channels, cand[k], mode, s);
+                e = launch(cand[k], mode);
             if (e == hipSuccess)
                 e = hipEventRecord(ev1, s);
             if (e == hipSuccess)

@@ -87,13 +87,15 @@ __device__ __forceinline__ float u8_to_f32(uint32_t word, int byte)
     return static_cast<float>((word >> (8 * byte)) & 0xffu);
 }
 
-// Round half to even, clamp to [0, 255].
-__device__ __forceinline__ uint32_t f32_to_u8(float v)
+// uint8 storage: round half to even, clamp to [0, 255]. v_cvt_pk_u8_f32 does
+// exactly this on gfx950 (it rounds in the default round-to-nearest-even mode
+// and saturates), and writes the byte into lane `byte` of `old`.
+__device__ __forceinline__ uint32_t u8_insert(float v, int byte, uint32_t old)
 {
-    v = __builtin_rintf(v);
-    v = __builtin_fminf(__builtin_fmaxf(v, 0.0f), 255.0f);
-    return static_cast<uint32_t>(v);
+    return __builtin_amdgcn_cvt_pk_u8_f32(v, byte, old);
 }
+
+__device__ __forceinline__ uint32_t f32_to_u8(float v) { return u8_insert(v, 0, 0u); }
 
 template <typename T, int C>
 struct Pix;
@@ -124,8 +126,10 @@ struct Pix<uint8_t, 4> {
     }
     __device__ __forceinline__ static uint32_t pack(const float (&v)[4])
     {
-        return f32_to_u8(v[0]) | (f32_to_u8(v[1]) << 8) | (f32_to_u8(v[2]) << 16) |
-               (f32_to_u8(v[3]) << 24);
+        uint32_t r = u8_insert(v[0], 0, 0u);
+        r = u8_insert(v[1], 1, r);
+        r = u8_insert(v[2], 2, r);
+        return u8_insert(v[3], 3, r);
     }
     __device__ __forceinline__ static void store(unsigned char *row, int32_t col, const float (&v)[4])
     {

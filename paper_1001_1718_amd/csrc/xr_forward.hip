@@ -20,6 +20,8 @@
 // (xr_device.hpp), so their results are bit-identical.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "xr_device.hpp"
 #include "xr_internal.h"
 
@@ -228,59 +230,107 @@ __global__ void __launch_bounds__(256) k_strip(ResizeArgs a, int32_t strip_h)
 // k_strip_up2 (exact x2 upscale on both axes)
 // ---------------------------------------------------------------------------
 
-template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h)
+// Copy one pixel of PB bytes between PB-aligned addresses.
+template <int PB>
+__device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned char *src)
 {
-    using TP = Taps<FILTER>;
-    constexpr int K = TP::K;
-    constexpr int M = PPX / 2;           // source columns owned per thread
-    constexpr int SPAN = M + K;          // source columns read per row
-    constexpr int PB = Pix<T, C>::kBytes;
-    // byte offset of the run start is (M*thread - K/2) * PB, plus a 16-byte
-    // aligned base when the caller's buffers allow it
-    constexpr int RUN_ALIGN = cmin(16, cgcd(M * PB, (K / 2) * PB));
-    constexpr int OUT_ALIGN = cmin(16, PPX * PB);
+    if constexpr (PB == 1) {
+        *dst = *src;
+    } else if constexpr (PB == 2) {
+        *reinterpret_cast<uint16_t *>(dst) = *reinterpret_cast<const uint16_t *>(src);
+    } else if constexpr (PB == 4) {
+        *reinterpret_cast<uint32_t *>(dst) = *reinterpret_cast<const uint32_t *>(src);
+    } else if constexpr (PB == 8) {
+        *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+    } else {
+        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+    }
+}
 
-    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
-    const int32_t r_begin = strip_begin(strip_h);
-    if (col0 >= a.out_w || r_begin >= a.dst_rows)
-        return;
-    const int32_t k0 = col0 / 2;
-    const int32_t run0 = k0 - K / 2;
-    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
-    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
-    const int32_t plane = blockIdx.z;
-
-    // t = 3/4 on even outputs, 1/4 on odd outputs (s(x) = (2x - 1)/4)
-    float we[K], wo[K];
-    weights<FILTER>(0.75f, 0.25f, we);
-    weights<FILTER>(0.25f, 0.75f, wo);
-
-    const bool interior = run0 >= 0 && run0 + SPAN <= a.in_w && col0 + PPX <= a.out_w;
-    const bool wide = interior && a.aligned16;
-    int32_t sx[SPAN];
+// Encode N pixels into a byte buffer (uint8 pixels four to a dword).
+template <typename T, int C, int N, int BYTES, int ALIGN>
+__device__ __forceinline__ void encode_run(const float (&v)[N][C], RawBuf<BYTES, ALIGN> &out)
+{
+    if constexpr (std::is_same<T, uint8_t>::value && C == 1 && N % 4 == 0) {
 #pragma unroll
-    for (int s = 0; s < SPAN; ++s)
-        sx[s] = clampi(run0 + s, 0, a.in_w - 1);
-
-    const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
-    unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
-
-    // source row r -> horizontally filtered values of the PPX output columns
-    auto hrow = [&](int32_t r, float (&out)[PPX][C]) {
-        const int32_t rr = clampi(r, 0, a.in_h - 1) - a.src_row0;
-        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
-        float p[SPAN][C];
-        if (wide) {
-            const auto raw = load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
-#pragma unroll
-            for (int s = 0; s < SPAN; ++s)
-                decode<T, C>(raw.b, s, p[s]);
-        } else {
-#pragma unroll
-            for (int s = 0; s < SPAN; ++s)
-                Pix<T, C>::load(row, sx[s], p[s]);
+        for (int g = 0; g < N / 4; ++g) {
+            uint32_t r = u8_insert(v[4 * g][0], 0, 0u);
+            r = u8_insert(v[4 * g + 1][0], 1, r);
+            r = u8_insert(v[4 * g + 2][0], 2, r);
+            r = u8_insert(v[4 * g + 3][0], 3, r);
+            *reinterpret_cast<uint32_t *>(out.b + 4 * g) = r;
         }
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+            Pix<T, C>::store(out.b, c, v[c]);
+    }
+}
+
+// One thread's walk down its strip. WIDE: the thread's source run and output
+// run lie inside the image and the buffers are 16-byte aligned, so rows move
+// with wide vector loads and stores; otherwise every pixel is loaded from its
+// clamped column and stores are masked at the right edge.
+template <int FILTER, typename T, int C, int PPX, bool WIDE>
+struct Up2Walk {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+    static constexpr int M = PPX / 2;   // source columns owned per thread
+    static constexpr int SPAN = M + K;  // source columns read per row
+    static constexpr int PB = Pix<T, C>::kBytes;
+    // byte offset of the run start is (M*thread - K/2) * PB
+    static constexpr int RUN_ALIGN = WIDE ? cmin(16, cgcd(M * PB, (K / 2) * PB)) : PB;
+    static constexpr int OUT_ALIGN = cmin(16, PPX * PB);
+    using Raw = RawBuf<SPAN * PB, RUN_ALIGN>;
+
+    const ResizeArgs &a;
+    const unsigned char *src;
+    unsigned char *dst;
+    int32_t col0, run0, y_b, y_e;
+    float we[K], wo[K];
+    // Source row r_first + i sits in ring slot i % K once filtered, and its raw
+    // bytes in queue slot i % Q from the time it is requested (PD rows ahead
+    // of the row being filtered) until it is filtered. The walk is unrolled by
+    // 4 rows, a multiple of K and Q, so every slot index is a constant.
+    static constexpr int PD = (SPAN * PB <= 32) ? 3 : 1;  // prefetch distance in rows
+    static constexpr int Q = PD + 1;
+    float ring[K][PPX][C];
+    Raw rawq[Q];
+
+    __device__ __forceinline__ Up2Walk(const ResizeArgs &a_, const unsigned char *s,
+                                       unsigned char *d, int32_t c0, int32_t yb, int32_t ye)
+        : a(a_), src(s), dst(d), col0(c0), run0(c0 / 2 - K / 2), y_b(yb), y_e(ye)
+    {
+        // t = 3/4 on even outputs, 1/4 on odd outputs (s(x) = (2x - 1)/4)
+        weights<FILTER>(0.75f, 0.25f, we);
+        weights<FILTER>(0.25f, 0.75f, wo);
+    }
+
+    // Rows are clamped into the stored band, which holds every row a needed
+    // tap reads (after clamping to the image); rows requested beyond the end
+    // of the walk are therefore valid addresses, merely unused.
+    __device__ __forceinline__ Raw load_row(int32_t r) const
+    {
+        const int32_t rr = clampi(r, a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
+        if constexpr (WIDE) {
+            return load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
+        } else {
+            Raw raw;
+#pragma unroll
+            for (int s = 0; s < SPAN; ++s)
+                copy_pixel<PB>(raw.b + s * PB,
+                               row + static_cast<int64_t>(clampi(run0 + s, 0, a.in_w - 1)) * PB);
+            return raw;
+        }
+    }
+
+    __device__ __forceinline__ void hfilter(const Raw &raw, float (&out)[PPX][C]) const
+    {
+        float p[SPAN][C];
+#pragma unroll
+        for (int s = 0; s < SPAN; ++s)
+            decode<T, C>(raw.b, s, p[s]);
 #pragma unroll
         for (int q = 0; q < M; ++q) {
             fma_first(out[2 * q], we[0], p[q]);
@@ -292,58 +342,97 @@ __global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h
             for (int i = 1; i < K; ++i)
                 fma_next(out[2 * q + 1], wo[i], p[q + 1 + i]);
         }
-    };
+    }
 
-    const int32_t ncols = min(PPX, a.out_w - col0);
-    auto emit = [&](int32_t y, const float (&w)[K], const float (&ring)[K][PPX][C]) {
+    // output row y from the window whose oldest row sits in ring slot OLD
+    template <int OLD>
+    __device__ __forceinline__ void emit(int32_t y, const float (&w)[K])
+    {
         unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
         float v[PPX][C];
 #pragma unroll
         for (int c = 0; c < PPX; ++c) {
-            fma_first(v[c], w[0], ring[0][c]);
+            fma_first(v[c], w[0], ring[OLD % K][c]);
 #pragma unroll
             for (int j = 1; j < K; ++j)
-                fma_next(v[c], w[j], ring[j][c]);
+                fma_next(v[c], w[j], ring[(OLD + j) % K][c]);
         }
-        if (wide) {
+        if constexpr (WIDE) {
             RawBuf<PPX * PB, OUT_ALIGN> out;
-#pragma unroll
-            for (int c = 0; c < PPX; ++c)
-                Pix<T, C>::store(out.b, c, v[c]);
+            encode_run<T, C, PPX>(v, out);
             store_raw<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
         } else {
+            const int32_t ncols = min(PPX, a.out_w - col0);
 #pragma unroll
             for (int c = 0; c < PPX; ++c)
                 if (c < ncols)
                     Pix<T, C>::store(drow, col0 + c, v[c]);
         }
-    };
+    }
 
-    // After filtering source row r the ring holds rows r-K+1 .. r, which are
-    // exactly the taps of output rows 2r-K+1 (odd, t = 1/4) and 2r-K+2 (even,
-    // t = 3/4).
-    const int32_t r_min = (y_b + K - 2 + 1) >> 1;   // ceil((y_b + K - 2) / 2), y_b >= 0
-    const int32_t r_max = (y_e - 1 + K - 1) >> 1;   // floor((y_e - 1 + K - 1) / 2)
-    float ring[K][PPX][C];
-#pragma unroll
-    for (int j = 0; j + 1 < K; ++j)
-        hrow(r_min - K + 1 + j, ring[j + 1]);
-#pragma unroll 4
-    for (int32_t r = r_min; r <= r_max; ++r) {
-#pragma unroll
-        for (int j = 0; j + 1 < K; ++j)
-#pragma unroll
-            for (int c = 0; c < PPX; ++c)
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    ring[j][c][ch] = ring[j + 1][c][ch];
-        hrow(r, ring[K - 1]);
+    // Filter source row r = r_first + I and emit the two output rows whose
+    // taps are rows r-K+1 .. r: 2r-K+1 (odd, t = 1/4) and 2r-K+2 (even,
+    // t = 3/4). Slots depend on I modulo 4 only. The load of row r + PD is
+    // issued unconditionally, so no branch separates a load from its use and
+    // the wait before filtering covers that one row only.
+    template <int I>
+    __device__ __forceinline__ void step(int32_t r)
+    {
+        rawq[(I + PD) % Q] = load_row(r + PD);
+        hfilter(rawq[I % Q], ring[I % K]);
         const int32_t y_odd = 2 * r - K + 1;
-        const int32_t y_even = y_odd + 1;
         if (y_odd >= y_b && y_odd < y_e)
-            emit(y_odd, wo, ring);
-        if (y_even >= y_b && y_even < y_e)
-            emit(y_even, we, ring);
+            emit<I + 1>(y_odd, wo);
+        if (y_odd + 1 >= y_b && y_odd + 1 < y_e)
+            emit<I + 1>(y_odd + 1, we);
+    }
+
+    __device__ __forceinline__ void run()
+    {
+        // rows r_min .. r_max produce the output rows [y_b, y_e); the walk
+        // runs in groups of 4 rows, so up to 3 rows past r_max are filtered
+        // without emitting anything
+        const int32_t r_min = (y_b + K - 2 + 1) >> 1;  // ceil((y_b + K - 2) / 2), y_b >= 0
+        const int32_t r_max = (y_e - 1 + K - 1) >> 1;  // floor((y_e - 1 + K - 1) / 2)
+        const int32_t r_first = r_min - K + 1;
+#pragma unroll
+        for (int i = 0; i < PD; ++i)
+            rawq[i % Q] = load_row(r_first + i);
+#pragma unroll
+        for (int i = 0; i + 1 < K; ++i) {  // rows r_first .. r_min - 1
+            rawq[(i + PD) % Q] = load_row(r_first + i + PD);
+            hfilter(rawq[i % Q], ring[i % K]);
+        }
+        for (int32_t r = r_min; r <= r_max; r += 4) {
+            step<K - 1>(r);
+            step<K>(r + 1);
+            step<K + 1>(r + 2);
+            step<K + 2>(r + 3);
+        }
+    }
+};
+
+template <int FILTER, typename T, int C, int PPX>
+__global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h)
+{
+    constexpr int K = Taps<FILTER>::K;
+    constexpr int SPAN = PPX / 2 + K;
+    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(strip_h);
+    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+        return;
+    const int32_t run0 = col0 / 2 - K / 2;
+    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
+    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
+    const bool wide = a.aligned16 && run0 >= 0 && run0 + SPAN <= a.in_w && col0 + PPX <= a.out_w;
+    if (wide) {
+        Up2Walk<FILTER, T, C, PPX, true> w(a, src, dst, col0, y_b, y_e);
+        w.run();
+    } else {
+        Up2Walk<FILTER, T, C, PPX, false> w(a, src, dst, col0, y_b, y_e);
+        w.run();
     }
 }
 
@@ -477,8 +566,8 @@ bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
 {
     (void)dtype;
     if (channels == 4)
-        return ppx == 2 || ppx == 4;
-    return ppx == 4 || ppx == 8;
+        return ppx == 2 || ppx == 4 || ppx == 8;
+    return ppx == 4 || ppx == 8 || ppx == 16;
 }
 
 namespace {
@@ -511,6 +600,7 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
         switch (tile.ppt_x) {
             XR_STRIP_CASE(2)
             XR_STRIP_CASE(4)
+            XR_STRIP_CASE(8)
         default:
             return hipErrorInvalidValue;
         }
@@ -518,6 +608,7 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
         switch (tile.ppt_x) {
             XR_STRIP_CASE(4)
             XR_STRIP_CASE(8)
+            XR_STRIP_CASE(16)
         default:
             return hipErrorInvalidValue;
         }

@@ -19,6 +19,7 @@ struct ResizeArgs {
     int32_t in_w, in_h;      // full logical source size
     int32_t out_w, out_h;    // full logical destination size
     int32_t src_row0;        // logical row stored first in src
+    int32_t src_rows;        // logical rows stored in src
     int32_t dst_row0;        // first logical output row to compute
     int32_t dst_rows;        // number of output rows to compute
     int32_t planes;

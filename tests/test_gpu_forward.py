@@ -128,3 +128,20 @@ def test_c2_rgba_u8_bicubic_sampled(direction):
     rows = np.unique(np.concatenate([[0, 1, 2, out - 2, out - 1], rng.integers(0, out, 40)]))
     got = y[torch.from_numpy(rows).to(DEV)].cpu().numpy()
     assert compare(got[None], img, out, out, 1, rows=rows, what=f"C2 {direction}") == 0
+
+
+def test_autotune_choice_does_not_change_results():
+    img = fields.uniform_u8((300, 260, 4), seed=17)
+    x = torch.from_numpy(img).to(DEV)
+    before = xr.resize(x, (600, 520), "bicubic").cpu().numpy()
+    srcs = [x, x.clone()]
+    dsts = [torch.empty((600, 520, 4), dtype=torch.uint8, device=DEV) for _ in range(2)]
+    cands = xr.tune_candidates("bicubic", xr.XR_U8, 4, 260, 300, 520, 600)
+    best, ms = xr.autotune(srcs, dsts, "bicubic", candidates=cands, reps=2, groups=2)
+    assert ms > 0 and best.kernel in (xr.XR_KERNEL_GATHER, xr.XR_KERNEL_STRIP)
+    assert xr.get_tile("bicubic", xr.XR_U8, 4, 260, 300, 520, 600).as_tuple() == best.as_tuple()
+    after = xr.resize(x, (600, 520), "bicubic").cpu().numpy()
+    np.testing.assert_array_equal(after, before)
+    for d in dsts:
+        np.testing.assert_array_equal(d.cpu().numpy(), before)
+    xr.set_tile("bicubic", xr.XR_U8, 4, 260, 300, 520, 600, xr.tile(xr.XR_KERNEL_AUTO))
