@@ -120,7 +120,10 @@ def headline(args, torch, xr, fields):
 
     tile = None
     tune = None
-    if not args.no_tune:
+    if args.tile:
+        xr.set_tile("bicubic", xr.XR_U8, ch, in_hw, in_hw, out_hw, out_hw,
+                    xr.tile(*(int(v) for v in args.tile.split(","))))
+    elif not args.no_tune:
         cands = [c for c in xr.tune_candidates("bicubic", xr.XR_U8, ch, in_hw, in_hw, out_hw, out_hw)
                  if c.kernel == xr.XR_KERNEL_STRIP]
         t0 = time.perf_counter()
@@ -352,6 +355,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
     ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--tile", type=str, default=None,
+                    help="fixed launch shape KIND,BW,BH,PPX,PPY[,ORDER] (kind 1 gather, 2 strip) instead of tuning")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for hardware counters)")
     args = ap.parse_args()

@@ -97,10 +97,14 @@ typedef struct {
  *         = XR_KERNEL_STRIP   : each thread walks ppt_y rows down a strip of
  *                               ppt_x columns and reuses the filtered rows
  *                               from registers; block_w a multiple of 64 and
- *                               block_w * block_h <= 256. An exact x2 upscale
+ *                               block_w * block_h <= 512. An exact x2 upscale
  *                               on both axes runs a variant specialised for it.
  *         = XR_KERNEL_STRIP_ANY : the strip kernel without the x2 variant (the
  *                               same results; for comparisons)
+ *  order  = 0 : tiles are processed in launch order (row-major)
+ *         = 1 : the launch is split into 8 contiguous bands of tiles, one per
+ *               XCD (the hardware deals workgroups to the 8 XCDs in turn), so
+ *               each XCD's L2 sees vertically adjacent tiles (strip kernels)
  */
 #define XR_KERNEL_AUTO 0
 #define XR_KERNEL_GATHER 1
@@ -113,6 +117,7 @@ typedef struct {
     int32_t block_h;
     int32_t ppt_x;
     int32_t ppt_y;
+    int32_t order;
 } xr_tile;
 
 /*
@@ -170,9 +175,12 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
  * sizes; every output pixel scatters wy_j * wx_i * g onto its clamped taps
  * (the transpose of eq. 5). float32, whole images only (row0 = 0,
  * rows = height on both), planes map one to one, channels 1 or 4.
- * grad_src is OVERWRITTEN. Contributions are summed in LDS per output tile and
- * merged across tiles with float32 atomics, so the summation order (not the
- * set of terms) may differ between runs.
+ * grad_src is OVERWRITTEN: each workgroup owns a tile of grad_src, scatter-adds
+ * the contributions of every output pixel that touches the tile into LDS
+ * (LDS float atomics) and stores the tile once, so no global atomics are used.
+ * The order in which LDS contributions are summed (not the set of terms) may
+ * differ between runs. XR_ERR_SHAPE if the vertical upscale is too strong for
+ * one tile (more than about 190x).
  */
 int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32_t filter,
                        void *stream);

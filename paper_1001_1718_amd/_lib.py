@@ -54,15 +54,16 @@ class XrTile(ctypes.Structure):
         ("block_h", ctypes.c_int32),
         ("ppt_x", ctypes.c_int32),
         ("ppt_y", ctypes.c_int32),
+        ("order", ctypes.c_int32),
     ]
 
     def as_tuple(self):
-        return (self.kernel, self.block_w, self.block_h, self.ppt_x, self.ppt_y)
+        return (self.kernel, self.block_w, self.block_h, self.ppt_x, self.ppt_y, self.order)
 
     def __repr__(self):
         kind = {0: "auto", 1: "gather", 2: "strip", 3: "strip_any"}.get(self.kernel, str(self.kernel))
         return (f"XrTile({kind}, block={self.block_w}x{self.block_h}, "
-                f"ppt={self.ppt_x}x{self.ppt_y})")
+                f"ppt={self.ppt_x}x{self.ppt_y}, order={self.order})")
 
 
 class XrJob(ctypes.Structure):
@@ -126,5 +127,5 @@ def check(code: int, where: str) -> None:
 
 
 def tile(kernel: int = XR_KERNEL_AUTO, block_w: int = 0, block_h: int = 0, ppt_x: int = 1,
-         ppt_y: int = 1) -> XrTile:
-    return XrTile(int(kernel), int(block_w), int(block_h), int(ppt_x), int(ppt_y))
+         ppt_y: int = 1, order: int = 0) -> XrTile:
+    return XrTile(int(kernel), int(block_w), int(block_h), int(ppt_x), int(ppt_y), int(order))

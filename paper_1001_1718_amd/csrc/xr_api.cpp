@@ -227,16 +227,19 @@ xr_tile default_tile(int32_t channels)
 {
     xr_tile t{};
     t.kernel = XR_KERNEL_STRIP;
-    t.block_w = 64;
-    t.block_h = 4;
+    t.block_w = 256;
+    t.block_h = 1;
     t.ppt_x = channels == 4 ? 4 : 8;
-    t.ppt_y = 32;
+    t.ppt_y = 14;
+    t.order = 0;
     return t;
 }
 
 int check_tile(const xr_tile &t, int32_t dtype, int32_t channels)
 {
     if (t.kernel == XR_KERNEL_GATHER) {
+        if (t.order != 0)
+            return fail(XR_ERR_ARG, "the gather kernel takes order = 0");
         if (t.block_w < 1 || t.block_h < 1 || t.block_w * t.block_h > 1024 || t.ppt_x != 1 ||
             t.ppt_y != 1)
             return fail(XR_ERR_ARG, "gather tile %dx%d (ppt %dx%d) invalid: need 1..1024 threads, ppt 1x1",
@@ -244,10 +247,12 @@ int check_tile(const xr_tile &t, int32_t dtype, int32_t channels)
         return XR_OK;
     }
     if (t.kernel == XR_KERNEL_STRIP || t.kernel == XR_KERNEL_STRIP_ANY) {
-        if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256)
+        if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 512)
             return fail(XR_ERR_ARG,
-                        "strip tile block %dx%d invalid: block_w a multiple of 64, at most 256 threads",
+                        "strip tile block %dx%d invalid: block_w a multiple of 64, at most 512 threads",
                         t.block_w, t.block_h);
+        if (t.order != 0 && t.order != 1)
+            return fail(XR_ERR_ARG, "tile.order = %d (must be 0 or 1)", t.order);
         if (!xr::strip_ppx_supported(dtype, channels, t.ppt_x))
             return fail(XR_ERR_ARG, "strip ppt_x = %d not built for %d channels", t.ppt_x, channels);
         if (t.ppt_y < 1 || t.ppt_y > 4096)
@@ -492,6 +497,9 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
     a.dst = static_cast<unsigned char *>(grad_src->data);
     a.dst_pitch = grad_src->row_pitch;
     a.dst_plane_pitch = grad_src->planes > 1 ? grad_src->plane_pitch : 0;
+    if (!xr::backward_supported(a, filter, grad_src->channels))
+        return fail(XR_ERR_SHAPE, "adjoint: %d -> %d rows is too strong an upscale for one LDS tile",
+                    grad_src->height, grad_dst->height);
     const hipError_t e = xr::launch_backward(a, filter, grad_src->channels, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "backward launch");
@@ -511,20 +519,21 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     const int gather[][2] = {{8, 8}, {32, 4}, {32, 16}, {4, 8}, {8, 4}, {16, 16}, {64, 4}, {64, 1},
                              {128, 2}, {256, 1}};
     for (const auto &g : gather)
-        c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1});
+        c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1, 0});
     const int ppx_c4[3] = {2, 4, 8};
     const int ppx_c1[3] = {4, 8, 16};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
-    const int blocks[][2] = {{64, 1}, {64, 2}, {64, 4}, {128, 1}, {128, 2}, {256, 1}};
+    const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}, {256, 2}, {512, 1}};
     // strip heights 8m-2 make the x2 walk's source-row groups come out even
-    const int ppy_list[] = {8, 14, 16, 30, 32, 62, 64, 126};
+    const int ppy_list[] = {6, 14, 22, 30, 46, 62};
     for (int k = 0; k < 3; ++k) {
         const int ppx = ppx_list[k];
         if (!xr::strip_ppx_supported(dtype, channels, ppx))
             continue;
         for (const auto &b : blocks)
             for (int ppy : ppy_list)
-                c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy});
+                for (int order = 0; order < 2; ++order)
+                    c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, order});
     }
     if (out)
         for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)

@@ -1,19 +1,26 @@
 // Adjoint of the resize with respect to its input, float32, for gfx950.
 //
-// grad_src = A^T grad_dst: every output pixel (y, x) scatters
+// grad_src = A_y^T grad_dst A_x: every output pixel (y, x) scatters
 // wy_j * wx_i * g[y][x] onto its clamped taps (the transpose of eq. 5).
 //
-// One workgroup takes an output tile. Its contributions are accumulated in an
-// LDS copy of the tile's source footprint (LDS float atomics), then the
-// footprint is merged into global memory:
-//   * pixels that no neighbouring tile touches are written with plain stores;
-//   * pixels on the footprint ring that the left/right/upper/lower neighbour
-//     also touches are merged with global float32 atomics. Before the main
-//     kernel, a small fill kernel zeroes exactly those ring rows and columns.
-// When an axis shrinks some source pixels may be touched by no output at all,
-// so for any downscale the whole gradient is zeroed first and every footprint
-// pixel is merged with atomics.
+// Owner computes: a workgroup owns a tile of grad_src (input pixels) and
+// gathers every output pixel whose taps touch that tile, so each gradient
+// pixel is written exactly once with a plain store: no global atomics, no
+// clearing pass, and pixels no output touches come out as zero.
+//
+//  phase 0  taps (first row, K weights) of the output rows of the region;
+//  phase 1  horizontal adjoint, scatter-add in LDS: for every output pixel of
+//           the region, u[y][c] += wx_i(x) * g[y][x] on each tap c inside the
+//           tile (LDS float atomics, the only atomics of the kernel);
+//  phase 2  vertical adjoint, gather: grad[r][c] = sum over the output rows y
+//           whose taps include r of wy_j(y) * u[y][c], summed in ascending y.
+//
+// Floating-point order: each tile sums its LDS contributions in whatever
+// order the LDS atomics land, so results can differ between runs in the last
+// bits; the set of terms is exact.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "xr_device.hpp"
 #include "xr_internal.h"
@@ -23,235 +30,433 @@ using namespace dev;
 
 namespace {
 
-constexpr int kBwdBlockW = 64;
-constexpr int kBwdBlockH = 4;
-constexpr int kBwdRows = 8;  // output rows per thread
+constexpr int kBwdThreads = 256;
 
-template <int C>
-struct BwdPpx {
-    static constexpr int P = (C == 4) ? 1 : 4;  // output columns per thread
+// N bytes of float32 data moved as one aligned vector access
+template <int N>
+struct alignas(16) RawBytes {
+    float f[N / 4];
 };
 
-// first clamped source index a run of outputs [b, e) touches, and the last
+// First output index whose clamped taps reach source index >= c, for the
+// axis n_in -> n_out (the map is monotone; see eqs. 1-4).
 template <int FILTER>
-__device__ __forceinline__ int32_t first_tap(int32_t b, int32_t n_in, int32_t n_out)
+__device__ __forceinline__ int32_t first_output(int32_t c, int32_t n_in, int32_t n_out)
 {
-    int32_t x0;
-    float t, u;
-    axis_tap(b, n_in, n_out, x0, t, u);
-    return clampi(x0 + Taps<FILTER>::LO, 0, n_in - 1);
+    using TP = Taps<FILTER>;
+    if (c <= 0)
+        return 0;
+    // lo(x) + K - 1 >= c  <=>  floor(s(x)) >= m  <=>  s(x) >= m
+    const int64_t m = static_cast<int64_t>(c) - TP::K + 1 - TP::LO;
+    const int64_t num = 2 * static_cast<int64_t>(n_out) * m + n_out - n_in;
+    const int64_t den = 2 * static_cast<int64_t>(n_in);
+    const int64_t x = num >= 0 ? (num + den - 1) / den : -((-num) / den);  // ceil
+    return static_cast<int32_t>(x < 0 ? 0 : (x > n_out - 1 ? n_out - 1 : x));
 }
 
+// Last output index whose clamped taps reach source index <= c.
 template <int FILTER>
-__device__ __forceinline__ int32_t last_tap(int32_t e, int32_t n_in, int32_t n_out)
+__device__ __forceinline__ int32_t last_output(int32_t c, int32_t n_in, int32_t n_out)
 {
-    int32_t x0;
-    float t, u;
-    axis_tap(e - 1, n_in, n_out, x0, t, u);
-    return clampi(x0 + Taps<FILTER>::LO + Taps<FILTER>::K - 1, 0, n_in - 1);
-}
-
-// Zero the source rows shared by the tiles above and below each tile-row
-// boundary. blockIdx.y = boundary index - 1, blockIdx.z = plane.
-template <int FILTER, int C>
-__global__ void __launch_bounds__(256) k_bwd_zero_rows(ResizeArgs a, int32_t tile_h)
-{
-    const int32_t yb = (blockIdx.y + 1) * tile_h;
-    const int32_t r_first = first_tap<FILTER>(yb, a.in_h, a.out_h);
-    const int32_t r_last = last_tap<FILTER>(yb, a.in_h, a.out_h);
-    const int32_t col = blockIdx.x * blockDim.x + threadIdx.x;  // float index in the row
-    if (col >= a.in_w * C)
-        return;
-    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
-    for (int32_t r = r_first; r <= r_last; ++r)
-        reinterpret_cast<float *>(dst + static_cast<int64_t>(r) * a.dst_pitch)[col] = 0.0f;
-}
-
-// Zero the source columns shared by the tiles left and right of each tile-column
-// boundary. blockIdx.x = boundary index - 1, threads run down the rows.
-template <int FILTER, int C>
-__global__ void __launch_bounds__(256) k_bwd_zero_cols(ResizeArgs a, int32_t tile_w)
-{
-    const int32_t xb = (blockIdx.x + 1) * tile_w;
-    const int32_t c_first = first_tap<FILTER>(xb, a.in_w, a.out_w);
-    const int32_t c_last = last_tap<FILTER>(xb, a.in_w, a.out_w);
-    const int32_t r = blockIdx.y * blockDim.x + threadIdx.x;
-    if (r >= a.in_h)
-        return;
-    float *row = reinterpret_cast<float *>(a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
-                                           static_cast<int64_t>(r) * a.dst_pitch);
-    for (int32_t c = c_first; c <= c_last; ++c)
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            row[c * C + ch] = 0.0f;
-}
-
-// Zero a whole gradient image.
-template <int C>
-__global__ void __launch_bounds__(256) k_bwd_zero_all(ResizeArgs a)
-{
-    const int32_t col = blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= a.in_w * C)
-        return;
-    float *row = reinterpret_cast<float *>(a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
-                                           static_cast<int64_t>(blockIdx.y) * a.dst_pitch);
-    row[col] = 0.0f;
+    using TP = Taps<FILTER>;
+    if (c >= n_in - 1)
+        return n_out - 1;
+    // lo(x) <= c  <=>  floor(s(x)) <= c - LO  <=>  s(x) < c - LO + 1
+    const int64_t m = static_cast<int64_t>(c) - TP::LO + 1;
+    const int64_t num = 2 * static_cast<int64_t>(n_out) * m + n_out - n_in;
+    const int64_t den = 2 * static_cast<int64_t>(n_in);
+    const int64_t x = (num >= 0 ? (num + den - 1) / den : -((-num) / den)) - 1;  // ceil - 1
+    return static_cast<int32_t>(x < 0 ? 0 : (x > n_out - 1 ? n_out - 1 : x));
 }
 
 // a.src = grad_dst (out_w x out_h), a.dst = grad_src (in_w x in_h).
+// Tile: tw columns x th rows of grad_src; LDS holds max_rows x tw x C floats
+// of u plus max_rows x (K + 1) words of row taps.
 template <int FILTER, int C>
-__global__ void __launch_bounds__(256) k_bwd_scatter(ResizeArgs a, int32_t all_atomic)
+__global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t tw, int32_t th,
+                                                           int32_t max_rows)
 {
     using TP = Taps<FILTER>;
     constexpr int K = TP::K;
-    constexpr int P = BwdPpx<C>::P;
-    constexpr int TW = kBwdBlockW * P;
-    constexpr int TH = kBwdBlockH * kBwdRows;
-    extern __shared__ float acc[];
+    extern __shared__ float lds[];
+    const int32_t row_floats = tw * C;
+    float *u = lds;                                                           // [max_rows][tw*C]
+    int32_t *ylo = reinterpret_cast<int32_t *>(lds + max_rows * row_floats);  // [max_rows]
+    float *ywt = reinterpret_cast<float *>(ylo + max_rows);                   // [max_rows][K]
 
-    const int32_t xa = blockIdx.x * TW;
-    const int32_t ya = blockIdx.y * TH;
-    const int32_t xe = min(xa + TW, a.out_w);
-    const int32_t ye = min(ya + TH, a.out_h);
+    const int32_t c_a = blockIdx.x * tw;
+    const int32_t c_b = min(c_a + tw, a.in_w);
+    const int32_t r_a = blockIdx.y * th;
+    const int32_t r_b = min(r_a + th, a.in_h);
     const int32_t plane = blockIdx.z;
+    const int32_t xa = first_output<FILTER>(c_a, a.in_w, a.out_w);
+    const int32_t xb = last_output<FILTER>(c_b - 1, a.in_w, a.out_w);
+    const int32_t ya = first_output<FILTER>(r_a, a.in_h, a.out_h);
+    const int32_t yb = min(last_output<FILTER>(r_b - 1, a.in_h, a.out_h), ya + max_rows - 1);
+    const int32_t nrows = yb - ya + 1;
+    const int32_t tid = threadIdx.x;
 
-    const int32_t fa = first_tap<FILTER>(xa, a.in_w, a.out_w);
-    const int32_t fb = last_tap<FILTER>(xe, a.in_w, a.out_w);
-    const int32_t ra = first_tap<FILTER>(ya, a.in_h, a.out_h);
-    const int32_t rb = last_tap<FILTER>(ye, a.in_h, a.out_h);
-    const int32_t fw = fb - fa + 1;
-    const int32_t fh = rb - ra + 1;
-    const int32_t tid = threadIdx.y * blockDim.x + threadIdx.x;
-    const int32_t nthreads = blockDim.x * blockDim.y;
-
-    for (int32_t k = tid; k < fw * fh * C; k += nthreads)
-        acc[k] = 0.0f;
+    // phase 0: clear u, row taps of the region
+    for (int32_t k = tid; k < nrows * row_floats; k += kBwdThreads)
+        u[k] = 0.0f;
+    for (int32_t k = tid; k < nrows; k += kBwdThreads) {
+        int32_t y0;
+        float t, omt;
+        axis_tap(ya + k, a.in_h, a.out_h, y0, t, omt);
+        float w[K];
+        weights<FILTER>(t, omt, w);
+        ylo[k] = y0 + TP::LO;
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            ywt[k * K + j] = w[j];
+    }
     __syncthreads();
 
-    // scatter this thread's outputs into the LDS footprint
-    const int32_t xc = xa + threadIdx.x * P;
-    if (xc < xe) {
-        int32_t lx[P][K];
-        float wx[P][K];
+    // phase 1: horizontal adjoint of every output row of the region, into LDS.
+    // A thread takes XP adjacent output columns and walks the region's rows in
+    // groups of RU, issuing the group's loads before its LDS additions so that
+    // RU rows of loads are in flight at once.
+    const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+    constexpr int XP = (C == 4) ? 1 : 2;
+    constexpr int RU = 8;
+    for (int32_t xc = xa + tid * XP; xc <= xb; xc += kBwdThreads * XP) {
+        float wx[XP][K];
+        int32_t lc[XP][K];
 #pragma unroll
-        for (int c = 0; c < P; ++c) {
+        for (int p = 0; p < XP; ++p) {
+            const int32_t x = min(xc + p, xb);
             int32_t x0;
-            float t, u;
-            axis_tap(min(xc + c, xe - 1), a.in_w, a.out_w, x0, t, u);
-            weights<FILTER>(t, u, wx[c]);
+            float t, omt;
+            axis_tap(x, a.in_w, a.out_w, x0, t, omt);
+            weights<FILTER>(t, omt, wx[p]);
 #pragma unroll
-            for (int i = 0; i < K; ++i)
-                lx[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1) - fa;
-            if (xc + c >= xe) {
-#pragma unroll
-                for (int i = 0; i < K; ++i)
-                    wx[c][i] = 0.0f;
+            for (int i = 0; i < K; ++i) {
+                const int32_t c = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
+                lc[p][i] = (xc + p <= xb && c >= c_a && c < c_b) ? (c - c_a) * C : -1;
             }
         }
-        const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
-        const int32_t y_begin = ya + __builtin_amdgcn_readfirstlane(threadIdx.y * kBwdRows);
-        const int32_t y_end = min(y_begin + kBwdRows, ye);
-        for (int32_t y = y_begin; y < y_end; ++y) {
-            int32_t y0;
-            float ty, uy;
-            axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
-            float wy[K];
-            weights<FILTER>(ty, uy, wy);
-            const unsigned char *grow = gsrc + static_cast<int64_t>(y) * a.src_pitch;
-            float g[P][C];
+        const int32_t xl = min(xc + XP - 1, xb) - xc;  // last valid column offset
+        for (int32_t k0 = 0; k0 < nrows; k0 += RU) {
+            float g[RU][XP][C];
 #pragma unroll
-            for (int c = 0; c < P; ++c) {
-                if (xc + c < xe)
-                    Pix<float, C>::load(grow, xc + c, g[c]);
-                else
+            for (int q = 0; q < RU; ++q) {
+                const int32_t row = ya + min(k0 + q, nrows - 1);
+                const unsigned char *grow = gsrc + static_cast<int64_t>(row) * a.src_pitch;
 #pragma unroll
-                    for (int ch = 0; ch < C; ++ch)
-                        g[c][ch] = 0.0f;
+                for (int p = 0; p < XP; ++p)
+                    Pix<float, C>::load(grow, xc + min(p, xl), g[q][p]);
             }
 #pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const int32_t ly = clampi(y0 + TP::LO + j, 0, a.in_h - 1) - ra;
-                float *arow = acc + static_cast<int32_t>(ly * fw) * C;
+            for (int q = 0; q < RU; ++q) {
+                if (k0 + q < nrows) {
+                    float *urow = u + (k0 + q) * row_floats;
 #pragma unroll
-                for (int c = 0; c < P; ++c)
+                    for (int p = 0; p < XP; ++p)
 #pragma unroll
-                    for (int i = 0; i < K; ++i) {
-                        const float w = wy[j] * wx[c][i];
+                        for (int i = 0; i < K; ++i)
+                            if (lc[p][i] >= 0) {
 #pragma unroll
-                        for (int ch = 0; ch < C; ++ch)
-                            atomicAdd(arow + lx[c][i] * C + ch, w * g[c][ch]);
-                    }
+                                for (int ch = 0; ch < C; ++ch)
+                                    atomicAdd(urow + lc[p][i] + ch, wx[p][i] * g[q][p][ch]);
+                            }
+                }
             }
         }
     }
     __syncthreads();
 
-    // merge the footprint into global memory
-    int32_t up_last = -1, down_first = a.in_h, left_last = -1, right_first = a.in_w;
-    if (!all_atomic) {
-        if (ya > 0)
-            up_last = last_tap<FILTER>(ya, a.in_h, a.out_h);
-        if (ye < a.out_h)
-            down_first = first_tap<FILTER>(ye, a.in_h, a.out_h);
-        if (xa > 0)
-            left_last = last_tap<FILTER>(xa, a.in_w, a.out_w);
-        if (xe < a.out_w)
-            right_first = first_tap<FILTER>(xe, a.in_w, a.out_w);
-    }
+    // phase 2: vertical adjoint, one (column, channel) per thread
     unsigned char *gdst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
-    for (int32_t k = tid; k < fw * fh; k += nthreads) {
-        const int32_t r = ra + k / fw;
-        const int32_t c = fa + k % fw;
-        float *out = reinterpret_cast<float *>(gdst + static_cast<int64_t>(r) * a.dst_pitch) + c * C;
-        const float *v = acc + k * C;
-        const bool exclusive =
-            !all_atomic && r > up_last && r < down_first && c > left_last && c < right_first;
-        if (exclusive) {
+    const int32_t ncols = (c_b - c_a) * C;
+    for (int32_t f = tid; f < ncols; f += kBwdThreads) {
+        int32_t k_first = 0;  // first region row whose taps reach the current r
+        for (int32_t r = r_a; r < r_b; ++r) {
+            while (k_first < nrows && clampi(ylo[k_first] + K - 1, 0, a.in_h - 1) < r)
+                ++k_first;
+            float acc = 0.0f;
+            for (int32_t k = k_first; k < nrows && clampi(ylo[k], 0, a.in_h - 1) <= r; ++k) {
+                float w = 0.0f;
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                out[ch] = v[ch];
-        } else {
-#pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                unsafeAtomicAdd(out + ch, v[ch]);
+                for (int j = 0; j < K; ++j)
+                    if (clampi(ylo[k] + j, 0, a.in_h - 1) == r)
+                        w += ywt[k * K + j];
+                acc = __builtin_fmaf(w, u[k * row_floats + f], acc);
+            }
+            reinterpret_cast<float *>(gdst + static_cast<int64_t>(r) * a.dst_pitch)[c_a * C + f] = acc;
         }
     }
 }
 
-// Fallback for footprints too large for LDS (strong shrinking): every output
-// pixel adds its contributions straight to the zeroed gradient with atomics.
+// ---------------------------------------------------------------------------
+// Exact x2 upscale on both axes: transposed strip walk in registers
+// ---------------------------------------------------------------------------
+//
+// For out = 2 in, output x taps source lo(x) + i with lo(2m) = m - 1 + LO
+// (t = 3/4) and lo(2m+1) = m + LO (t = 1/4). Ignoring the clamp, source
+// column c therefore receives the 2K outputs x = 2c - K + 1 + d, d = 0..2K-1,
+// with weight wo[K-1-q] for d = 2q and we[K-1-q] for d = 2q+1; rows alike.
+// k_bwd_up2 sums exactly those unclamped terms (outputs outside the image
+// count as zero); k_bwd_up2_border then adds, for the source pixels on the
+// image border, the terms whose taps were clamped onto them.
+
+template <int FILTER, int C, int P>
+struct BwdUp2 {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+    static constexpr int W = 2 * P + 2 * K - 2;       // output pixels read per row
+    static constexpr int SX0 = (C == 1) ? -4 : 1 - K;  // first loaded pixel relative to 2*c0
+    static constexpr int SX = (C == 1) ? 16 : W;       // pixels loaded per row
+    static constexpr int OFF = (1 - K) - SX0;          // window start within the loaded pixels
+    static constexpr int Q = 2;                        // output rows per step
+};
+
+template <int FILTER, int C, int P>
+__global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
+{
+    using B = BwdUp2<FILTER, C, P>;
+    constexpr int K = B::K;
+    constexpr int SX = B::SX;
+    static_assert(C == 4 || P == 4, "float32 rows are read 16 pixels at a time");
+    float we[K], wo[K];
+    weights<FILTER>(0.75f, 0.25f, we);
+    weights<FILTER>(0.25f, 0.75f, wo);
+    float wt[2 * K];  // transposed weights over the window of one source index
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        wt[2 * q] = wo[K - 1 - q];
+        wt[2 * q + 1] = we[K - 1 - q];
+    }
+
+    const int32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * P;
+    const int32_t r_a = __builtin_amdgcn_readfirstlane(blockIdx.y * strip_h);
+    if (c0 >= a.in_w || r_a >= a.in_h)
+        return;
+    const int32_t r_b = min(r_a + strip_h, a.in_h);
+    const int32_t plane = blockIdx.z;
+    const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+    const int32_t xs = 2 * c0 + B::SX0;  // first loaded output column
+    const bool wide = a.aligned16 && xs >= 0 && xs + SX <= a.out_w && c0 + P <= a.in_w;
+
+    // one output row's pixels [xs, xs + SX), zero outside the image
+    auto load_row = [&](int32_t y, float (&v)[SX][C]) {
+        const bool row_ok = y >= 0 && y < a.out_h;
+        const int32_t yy = clampi(y, 0, a.out_h - 1);
+        const unsigned char *row = gsrc + static_cast<int64_t>(yy) * a.src_pitch;
+        if (wide) {
+            const auto raw = *reinterpret_cast<const RawBytes<SX * C * 4> *>(
+                __builtin_assume_aligned(row + static_cast<int64_t>(xs) * C * 4, 16));
+#pragma unroll
+            for (int s = 0; s < SX; ++s)
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    v[s][ch] = row_ok ? raw.f[s * C + ch] : 0.0f;
+        } else {
+#pragma unroll
+            for (int s = 0; s < SX; ++s) {
+                const int32_t x = xs + s;
+                const bool ok = row_ok && x >= 0 && x < a.out_w;
+                float p[C];
+                Pix<float, C>::load(row, clampi(x, 0, a.out_w - 1), p);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    v[s][ch] = ok ? p[ch] : 0.0f;
+            }
+        }
+    };
+    // horizontal adjoint of one output row for the P owned source columns
+    auto hadj = [&](const float (&v)[SX][C], float (&u)[P][C]) {
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            fma_first(u[p], wt[0], v[B::OFF + 2 * p]);
+#pragma unroll
+            for (int d = 1; d < 2 * K; ++d)
+                fma_next(u[p], wt[d], v[B::OFF + 2 * p + d]);
+        }
+    };
+
+    // ring of the horizontal adjoints of output rows y, slot (y - y_first) mod 2K
+    float ring[2 * K][P][C];
+    const int32_t y_first = 2 * r_a - K + 1;
+    float va[SX][C], vb[SX][C];
+#pragma unroll
+    for (int k = 0; k + 2 < 2 * K; k += 2) {  // rows y_first .. y_first + 2K - 3
+        load_row(y_first + k, va);
+        load_row(y_first + k + 1, vb);
+        hadj(va, ring[k]);
+        hadj(vb, ring[k + 1]);
+    }
+    unsigned char *gdst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
+    const int32_t ncols = min(P, a.in_w - c0);
+    auto step = [&](auto slot_tag, int32_t r) {
+        constexpr int S = decltype(slot_tag)::value;  // slot of the first new row
+        // rows 2r + K - 1 and 2r + K complete the window of source row r
+        load_row(2 * r + K - 1, va);
+        load_row(2 * r + K, vb);
+        hadj(va, ring[S % (2 * K)]);
+        hadj(vb, ring[(S + 1) % (2 * K)]);
+        float g[P][C];
+#pragma unroll
+        for (int p = 0; p < P; ++p) {
+            fma_first(g[p], wt[0], ring[(S + 2) % (2 * K)][p]);
+#pragma unroll
+            for (int d = 1; d < 2 * K; ++d)
+                fma_next(g[p], wt[d], ring[(S + 2 + d) % (2 * K)][p]);
+        }
+        unsigned char *drow = gdst + static_cast<int64_t>(r) * a.dst_pitch;
+        if (wide) {
+            RawBytes<P * C * 4> out;
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    out.f[p * C + ch] = g[p][ch];
+            *reinterpret_cast<RawBytes<P * C * 4> *>(
+                __builtin_assume_aligned(drow + static_cast<int64_t>(c0) * C * 4, 16)) = out;
+        } else {
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                if (p < ncols)
+                    Pix<float, C>::store(drow, c0 + p, g[p]);
+        }
+    };
+    // the window of row r starts at slot (2(r - r_a)) mod 2K; unroll K rows so
+    // that every slot index is a constant
+    for (int32_t r = r_a; r < r_b; r += K) {
+        step(std::integral_constant<int, 2 * K - 2>{}, r);
+        if (r + 1 < r_b)
+            step(std::integral_constant<int, 2 * K>{}, r + 1);
+        if constexpr (K == 4) {
+            if (r + 2 < r_b)
+                step(std::integral_constant<int, 2 * K + 2>{}, r + 2);
+            if (r + 3 < r_b)
+                step(std::integral_constant<int, 2 * K + 4>{}, r + 3);
+        }
+    }
+}
+
+// Border source pixels: add the terms whose row or column tap was clamped onto
+// them (the interior walk above left those out). One thread per border pixel
+// and plane; index k walks row 0, row in_h-1, then columns 0 and in_w-1 of
+// the rows in between.
 template <int FILTER, int C>
-__global__ void __launch_bounds__(256) k_bwd_direct(ResizeArgs a)
+__global__ void __launch_bounds__(256) k_bwd_up2_border(ResizeArgs a)
 {
     using TP = Taps<FILTER>;
     constexpr int K = TP::K;
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
-    if (x >= a.out_w || y >= a.out_h)
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t n_rows_part = (a.in_h > 1) ? 2 * a.in_w : a.in_w;
+    const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
+    const int32_t n_cols_part = (a.in_w > 1) ? 2 * inner : inner;
+    if (k >= n_rows_part + n_cols_part)
         return;
-    int32_t x0, y0;
-    float tx, ty, ux, uy;
-    axis_tap(x, a.in_w, a.out_w, x0, tx, ux);
-    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
-    float wx[K], wy[K];
-    weights<FILTER>(tx, ux, wx);
-    weights<FILTER>(ty, uy, wy);
-    float g[C];
-    Pix<float, C>::load(a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch +
-                            static_cast<int64_t>(y) * a.src_pitch,
-                        x, g);
-    unsigned char *gdst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
+    int32_t r, c;
+    if (k < n_rows_part) {
+        r = (k < a.in_w) ? 0 : a.in_h - 1;
+        c = k % a.in_w;
+    } else {
+        const int32_t j = k - n_rows_part;
+        r = 1 + j % inner;
+        c = (j < inner) ? 0 : a.in_w - 1;
+    }
+    const int32_t y_lo = first_output<FILTER>(r, a.in_h, a.out_h);
+    const int32_t y_hi = last_output<FILTER>(r, a.in_h, a.out_h);
+    const int32_t x_lo = first_output<FILTER>(c, a.in_w, a.out_w);
+    const int32_t x_hi = last_output<FILTER>(c, a.in_w, a.out_w);
+    const unsigned char *gsrc = a.src + static_cast<int64_t>(blockIdx.y) * a.src_plane_pitch;
+    float extra[C];
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const int32_t r = clampi(y0 + TP::LO + j, 0, a.in_h - 1);
-        float *row = reinterpret_cast<float *>(gdst + static_cast<int64_t>(r) * a.dst_pitch);
+    for (int ch = 0; ch < C; ++ch)
+        extra[ch] = 0.0f;
+    for (int32_t y = y_lo; y <= y_hi; ++y) {
+        int32_t y0;
+        float ty, uy;
+        axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+        float wy[K];
+        weights<FILTER>(ty, uy, wy);
+        const unsigned char *grow = gsrc + static_cast<int64_t>(y) * a.src_pitch;
+        for (int32_t x = x_lo; x <= x_hi; ++x) {
+            int32_t x0;
+            float tx, ux;
+            axis_tap(x, a.in_w, a.out_w, x0, tx, ux);
+            float wx[K];
+            weights<FILTER>(tx, ux, wx);
+            float w = 0.0f;
 #pragma unroll
-        for (int i = 0; i < K; ++i) {
-            const int32_t c = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
-            const float w = wy[j] * wx[i];
+            for (int j = 0; j < K; ++j) {
+                const int32_t ry = y0 + TP::LO + j;
+                if (clampi(ry, 0, a.in_h - 1) != r)
+                    continue;
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                unsafeAtomicAdd(row + c * C + ch, w * g[ch]);
+                for (int i = 0; i < K; ++i) {
+                    const int32_t cx = x0 + TP::LO + i;
+                    if (clampi(cx, 0, a.in_w - 1) == c && (ry != r || cx != c))
+                        w += wy[j] * wx[i];
+                }
+            }
+            if (w != 0.0f) {
+                float g[C];
+                Pix<float, C>::load(grow, x, g);
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    extra[ch] = __builtin_fmaf(w, g[ch], extra[ch]);
+            }
+        }
+    }
+    float *out = reinterpret_cast<float *>(a.dst + static_cast<int64_t>(blockIdx.y) * a.dst_plane_pitch +
+                                           static_cast<int64_t>(r) * a.dst_pitch) + c * C;
+#pragma unroll
+    for (int ch = 0; ch < C; ++ch)
+        out[ch] += extra[ch];
+}
+
+template <int FILTER, int C>
+hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
+{
+    constexpr int P = (C == 1) ? 4 : 1;
+    constexpr int32_t kStrip = 16;
+    const int32_t cols_per_block = 256 * P;
+    hipLaunchKernelGGL((k_bwd_up2<FILTER, C, P>),
+                       dim3((a.in_w + cols_per_block - 1) / cols_per_block, (a.in_h + kStrip - 1) / kStrip,
+                            a.planes),
+                       dim3(256), 0, stream, a, kStrip);
+    const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
+    const int32_t border = ((a.in_h > 1) ? 2 * a.in_w : a.in_w) + ((a.in_w > 1) ? 2 * inner : inner);
+    hipLaunchKernelGGL((k_bwd_up2_border<FILTER, C>), dim3((border + 255) / 256, a.planes), dim3(256), 0,
+                       stream, a);
+    return hipGetLastError();
+}
+
+// Tile of the owner-computes kernel: tw source columns (tw * C = 256 values
+// across the threads) and th source rows, shrunk until the region of output
+// rows fits the LDS budget.
+struct BwdPlan {
+    int32_t tw, th, max_rows;
+    size_t lds;
+};
+
+template <int FILTER, int C>
+BwdPlan plan_backward(const ResizeArgs &a)
+{
+    constexpr int K = Taps<FILTER>::K;
+    constexpr size_t kBudget = 64 * 1024;
+    BwdPlan p{};
+    p.tw = kBwdThreads / C;
+    p.th = 16;
+    for (;;) {
+        // output rows touching th source rows: at most (th + K - 1) * out/in + 2
+        const int64_t rows = (static_cast<int64_t>(p.th + K - 1) * a.out_h + a.in_h - 1) / a.in_h + 2;
+        p.max_rows = static_cast<int32_t>(rows);
+        p.lds = static_cast<size_t>(rows) * (p.tw * C * sizeof(float) + (K + 1) * sizeof(int32_t));
+        if (p.lds <= kBudget)
+            return p;
+        if (p.th > 1) {
+            p.th /= 2;
+        } else if (p.tw > 16) {
+            p.tw /= 2;
+            p.th = 16;
+        } else {
+            p.lds = 0;
+            return p;
         }
     }
 }
@@ -259,44 +464,27 @@ __global__ void __launch_bounds__(256) k_bwd_direct(ResizeArgs a)
 template <int FILTER, int C>
 hipError_t launch_bwd_typed(const ResizeArgs &a, hipStream_t stream)
 {
-    constexpr int K = Taps<FILTER>::K;
-    constexpr int TW = kBwdBlockW * BwdPpx<C>::P;
-    constexpr int TH = kBwdBlockH * kBwdRows;
-    const int32_t tiles_x = (a.out_w + TW - 1) / TW;
-    const int32_t tiles_y = (a.out_h + TH - 1) / TH;
-    const bool all_atomic = a.in_w > a.out_w || a.in_h > a.out_h;
-    // largest footprint of a tile: (T-1) * in/out + 1 + K per axis
-    const int64_t fw = (static_cast<int64_t>(TW - 1) * a.in_w) / a.out_w + K + 2;
-    const int64_t fh = (static_cast<int64_t>(TH - 1) * a.in_h) / a.out_h + K + 2;
-    const size_t lds = static_cast<size_t>(fw) * fh * C * sizeof(float);
-    const int32_t row_threads = a.in_w * C;
-    if (lds > 64 * 1024) {
-        hipLaunchKernelGGL(k_bwd_zero_all<C>, dim3((row_threads + 255) / 256, a.in_h, a.planes),
-                           dim3(256), 0, stream, a);
-        hipLaunchKernelGGL((k_bwd_direct<FILTER, C>),
-                           dim3((a.out_w + 63) / 64, (a.out_h + 3) / 4, a.planes), dim3(64, 4), 0,
-                           stream, a);
-        return hipGetLastError();
-    }
-    if (all_atomic) {
-        hipLaunchKernelGGL(k_bwd_zero_all<C>, dim3((row_threads + 255) / 256, a.in_h, a.planes),
-                           dim3(256), 0, stream, a);
-    } else {
-        if (tiles_y > 1)
-            hipLaunchKernelGGL((k_bwd_zero_rows<FILTER, C>),
-                               dim3((row_threads + 255) / 256, tiles_y - 1, a.planes), dim3(256), 0,
-                               stream, a, TH);
-        if (tiles_x > 1)
-            hipLaunchKernelGGL((k_bwd_zero_cols<FILTER, C>),
-                               dim3(tiles_x - 1, (a.in_h + 255) / 256, a.planes), dim3(256), 0,
-                               stream, a, TW);
-    }
-    hipLaunchKernelGGL((k_bwd_scatter<FILTER, C>), dim3(tiles_x, tiles_y, a.planes),
-                       dim3(kBwdBlockW, kBwdBlockH), lds, stream, a, all_atomic ? 1 : 0);
+    if (a.out_w == 2 * a.in_w && a.out_h == 2 * a.in_h)
+        return launch_bwd_up2<FILTER, C>(a, stream);
+    const BwdPlan p = plan_backward<FILTER, C>(a);
+    if (p.lds == 0)
+        return hipErrorInvalidConfiguration;
+    const dim3 grid((a.in_w + p.tw - 1) / p.tw, (a.in_h + p.th - 1) / p.th, a.planes);
+    hipLaunchKernelGGL((k_bwd_owner<FILTER, C>), grid, dim3(kBwdThreads), p.lds, stream, a, p.tw, p.th,
+                       p.max_rows);
     return hipGetLastError();
 }
 
 }  // namespace
+
+bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels)
+{
+    if (filter == XR_BICUBIC)
+        return channels == 4 ? plan_backward<kBicubic, 4>(a).lds != 0
+                             : plan_backward<kBicubic, 1>(a).lds != 0;
+    return channels == 4 ? plan_backward<kBilinear, 4>(a).lds != 0
+                         : plan_backward<kBilinear, 1>(a).lds != 0;
+}
 
 hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels, hipStream_t stream)
 {

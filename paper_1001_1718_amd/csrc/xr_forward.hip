@@ -206,19 +206,42 @@ struct StripBody {
     }
 };
 
+// Logical tile (bx, by) of this workgroup within its plane. order 0 keeps the
+// launch order. order 1 relies on the hardware dealing consecutive workgroups
+// to the 8 XCDs in turn and gives XCD k the k-th contiguous band of tiles
+// (a bijection for any tile count), so neighbouring tiles share an L2.
+__device__ __forceinline__ void tile_coords(int32_t order, int32_t &bx, int32_t &by)
+{
+    if (order == 0) {
+        bx = blockIdx.x;
+        by = blockIdx.y;
+        return;
+    }
+    const uint32_t gx = gridDim.x;
+    const uint32_t n = gx * gridDim.y;
+    const uint32_t h = blockIdx.y * gx + blockIdx.x;
+    const uint32_t q = n / 8, r = n % 8;
+    const uint32_t xcd = h % 8, slot = h / 8;
+    const uint32_t logical = xcd * q + min(xcd, r) + slot;
+    bx = static_cast<int32_t>(logical % gx);
+    by = static_cast<int32_t>(logical / gx);
+}
+
 // Row strip of a thread: threadIdx.y selects one of blockDim.y strips stacked
 // vertically in the tile. blockDim.x is a multiple of the wavefront size, so
 // the strip is uniform across a wavefront.
-__device__ __forceinline__ int32_t strip_begin(int32_t strip_h)
+__device__ __forceinline__ int32_t strip_begin(int32_t by, int32_t strip_h)
 {
-    return __builtin_amdgcn_readfirstlane((blockIdx.y * blockDim.y + threadIdx.y) * strip_h);
+    return __builtin_amdgcn_readfirstlane((by * static_cast<int32_t>(blockDim.y) + threadIdx.y) * strip_h);
 }
 
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(256) k_strip(ResizeArgs a, int32_t strip_h)
+__global__ void __launch_bounds__(512) k_strip(ResizeArgs a, int32_t strip_h, int32_t order)
 {
-    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
-    const int32_t r_begin = strip_begin(strip_h);
+    int32_t bx, by;
+    tile_coords(order, bx, by);
+    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(by, strip_h);
     if (col0 >= a.out_w || r_begin >= a.dst_rows)
         return;
     const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
@@ -413,12 +436,14 @@ struct Up2Walk {
 };
 
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(256) k_strip_up2(ResizeArgs a, int32_t strip_h)
+__global__ void __launch_bounds__(512) k_strip_up2(ResizeArgs a, int32_t strip_h, int32_t order)
 {
     constexpr int K = Taps<FILTER>::K;
     constexpr int SPAN = PPX / 2 + K;
-    const int32_t col0 = (blockIdx.x * blockDim.x + threadIdx.x) * PPX;
-    const int32_t r_begin = strip_begin(strip_h);
+    int32_t bx, by;
+    tile_coords(order, bx, by);
+    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(by, strip_h);
     if (col0 >= a.out_w || r_begin >= a.dst_rows)
         return;
     const int32_t run0 = col0 / 2 - K / 2;
@@ -591,10 +616,10 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
     case P:                                                                                \
         if (mode == kUp2)                                                                  \
             hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,  \
-                               tile.ppt_y);                                                \
+                               tile.ppt_y, tile.order);                                    \
         else                                                                               \
             hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a,      \
-                               tile.ppt_y);                                                \
+                               tile.ppt_y, tile.order);                                    \
         return hipGetLastError();
     if constexpr (C == 4) {
         switch (tile.ppt_x) {

@@ -61,6 +61,9 @@ hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_
 int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads);
 hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels,
                            hipStream_t stream);
+// False when one source row's output rows cannot fit the adjoint's LDS tile
+// (vertical upscale beyond roughly 190x).
+bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels);
 
 // Pixels per thread along x that the strip kernel is instantiated for.
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx);

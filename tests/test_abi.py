@@ -114,6 +114,12 @@ CASES = [
                                                    tile=xr.tile(xr.XR_KERNEL_STRIP, 32, 4, 8, 8)), 11),
     ("strip ppt not built", lambda: _fwd(_img(), _img(32, 32, data=D2),
                                          tile=xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 3, 8)), 11),
+    ("strip too many threads", lambda: _fwd(_img(), _img(32, 32, data=D2),
+                                            tile=xr.tile(xr.XR_KERNEL_STRIP, 512, 2, 8, 8)), 11),
+    ("bad order", lambda: _fwd(_img(), _img(32, 32, data=D2),
+                               tile=xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 8, 8, 2)), 11),
+    ("gather with order", lambda: _fwd(_img(), _img(32, 32, data=D2),
+                                       tile=xr.tile(xr.XR_KERNEL_GATHER, 8, 8, 1, 1, 1)), 11),
 ]
 
 

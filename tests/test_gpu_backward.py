@@ -1,8 +1,8 @@
 """GPU parity of the adjoint (xr_resize_backward) and of the autograd wrapper.
 
-* small shapes of every filter and channel count (upscale, shrink, identity,
-  strong shrink that takes the LDS-free path) against the FP64 oracle adjoint,
-  within 1e-5 * sum |w_y w_x g| per pixel;
+* small shapes of every filter and channel count (exact x2 with its border
+  pass, other upscales, shrinking, identity, one-row and one-column sources)
+  against the FP64 oracle adjoint, within 1e-5 * sum |w_y w_x g| per pixel;
 * the finite-difference Jacobian of the oracle forward on a 16 x 16 x 1 crop;
 * the 32 x 3 x 1024^2 -> 2048^2 float32 workload: forward rows, adjoint
   planes, the adjoint identity <Ax, y> = <x, A^T y> and mass conservation.
@@ -34,13 +34,18 @@ def _adjoint_gpu(g_nchw: np.ndarray, in_h: int, in_w: int, mode: str) -> np.ndar
 
 
 SHAPES = [
-    ((37, 53), (74, 106)),   # x2 up, ragged: LDS path with ring atomics
+    ((37, 53), (74, 106)),   # x2 up, ragged
     ((20, 300), (90, 610)),  # several tiles in both directions
-    ((37, 53), (61, 29)),    # mixed: shrink along x -> all-atomic path
+    ((37, 53), (61, 29)),    # mixed: shrink along x
     ((64, 96), (32, 48)),    # x0.5
     ((33, 21), (33, 21)),    # identity
-    ((1, 5), (40, 7)),       # one source row
-    ((300, 280), (21, 17)),  # strong shrink: LDS-free fallback
+    ((1, 5), (40, 7)),       # one source row, strong vertical upscale (narrow tiles)
+    ((300, 280), (21, 17)),  # strong shrink: source pixels that no output touches
+    ((40, 700), (311, 1400)),  # several column tiles, non-dyadic rows
+    ((1, 6), (2, 12)),       # x2 with a single source row (border pass only)
+    ((5, 1), (10, 2)),       # x2 with a single source column
+    ((2, 2), (4, 4)),        # x2, every pixel on the border
+    ((48, 2050), (96, 4100)),  # x2, ragged last column block, several strips
 ]
 
 
@@ -148,3 +153,10 @@ def test_adjoint_overwrites_output():
     scale = R.adjoint(g.cpu().numpy().reshape(1, 80, 64, 1), 40, 32, 1, absolute=True)[0, :, :, 0]
     check_f32(first[0, 0].cpu().numpy(), ref, scale, what="first call")
     check_f32(out[0, 0].cpu().numpy(), ref, scale, what="second call")
+
+
+def test_adjoint_rejects_extreme_upscale():
+    g = torch.zeros((1, 1, 30000, 4), device=DEV)
+    with pytest.raises(xr.XResizeError) as e:
+        xr.resize_backward(g, (1, 4), "bicubic")
+    assert e.value.code == 2

@@ -29,6 +29,8 @@ TILES = {
     "gather32x4": xr.tile(xr.XR_KERNEL_GATHER, 32, 4),
     "strip": xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 0, 7),      # ppt_x filled per case
     "strip_any": xr.tile(xr.XR_KERNEL_STRIP_ANY, 128, 2, 0, 5),
+    "strip_xcd": xr.tile(xr.XR_KERNEL_STRIP, 512, 1, 0, 9, 1),
+    "strip_any_xcd": xr.tile(xr.XR_KERNEL_STRIP_ANY, 64, 2, 0, 3, 1),
 }
 
 
