@@ -277,6 +277,10 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         srcs = [src0] + [src0.clone() for _ in range(n_buf - 1)]
         dsts = [torch.empty(out_shape, dtype=src0.dtype, device=dev) for _ in range(n_buf)]
 
+        cands = [c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], src0.shape[-1] if layout == "hwc" and src0.dim() == 3 else 1,
+                                               1, 1, 1, 1) if c.kernel == xr.XR_KERNEL_STRIP]
+        tile, _ = xr.autotune(srcs, dsts, mode, layout=layout, candidates=cands, reps=4, groups=3)
+
         def launch(i):
             xr.resize_into(srcs[i], dsts[i], mode, layout=layout)
 
@@ -284,7 +288,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         k_s = sum(ms) / len(ms) / 1e3
         # pixels: H * W for interleaved images, N * C * H * W for planar tensors
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
-        out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2),
+        out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
                      "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
                      "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"extra {name}: {out[name]}")

@@ -223,7 +223,11 @@ TuneKey tune_key(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, 
 std::mutex g_tune_mu;
 std::map<TuneKey, xr_tile> g_tuned;
 
-xr_tile default_tile(int32_t channels)
+// Untuned launch shape: 256-wide workgroups (four wavefronts on the same
+// rows), 4 (RGBA) or 8 (one channel) columns per thread, and the longest
+// strip of the form 8m - 2 rows that still gives about 8 wavefronts per SIMD
+// (2048 x 4); small outputs fall back to narrower runs and single rows.
+xr_tile default_tile(int32_t channels, int32_t out_w, int32_t rows, int32_t planes)
 {
     xr_tile t{};
     t.kernel = XR_KERNEL_STRIP;
@@ -232,6 +236,19 @@ xr_tile default_tile(int32_t channels)
     t.ppt_x = channels == 4 ? 4 : 8;
     t.ppt_y = 14;
     t.order = 0;
+    const auto waves = [&](const xr_tile &u) {
+        const int64_t wcols = (static_cast<int64_t>(out_w) + 64 * u.ppt_x - 1) / (64 * u.ppt_x);
+        return wcols * ((static_cast<int64_t>(rows) + u.ppt_y - 1) / u.ppt_y) * planes;
+    };
+    const int64_t target = 8192;
+    const int steps[] = {14, 6, 2, 1};
+    for (int ppy : steps) {
+        t.ppt_y = ppy;
+        if (waves(t) >= target)
+            return t;
+    }
+    t.ppt_x = channels == 4 ? 2 : 4;
+    t.block_w = 64;
     return t;
 }
 
@@ -272,7 +289,7 @@ xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, c
     auto it = g_tuned.find(key);
     if (it != g_tuned.end())
         return it->second;
-    return default_tile(src.channels);
+    return default_tile(src.channels, dst.width, dst.rows, dst.planes);
 }
 
 int check_grid(const xr_tile &t, const xr_image &dst)
@@ -358,7 +375,7 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
         if (t.kernel != XR_KERNEL_STRIP)
             return fail(XR_ERR_ARG, "the batched launch takes a strip tile");
     } else {
-        t = default_tile(4);
+        t = xr_tile{XR_KERNEL_STRIP, 64, 4, xr::kBatchPpx, 8, 0};
     }
     t.ppt_x = xr::kBatchPpx;
     if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256 ||
@@ -671,7 +688,7 @@ int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
         return fail(XR_ERR_SHAPE, "sizes must be positive");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h));
-    *out = it != g_tuned.end() ? it->second : default_tile(channels);
+    *out = it != g_tuned.end() ? it->second : default_tile(channels, out_w, out_h, 1);
     return XR_OK;
 }
 

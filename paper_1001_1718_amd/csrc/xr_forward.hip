@@ -119,28 +119,70 @@ __global__ void __launch_bounds__(1024) k_gather(ResizeArgs a)
 // k_strip (any scale)
 // ---------------------------------------------------------------------------
 
+// Copy one pixel of PB bytes between PB-aligned addresses.
+template <int PB>
+__device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned char *src)
+{
+    if constexpr (PB == 1) {
+        *dst = *src;
+    } else if constexpr (PB == 2) {
+        *reinterpret_cast<uint16_t *>(dst) = *reinterpret_cast<const uint16_t *>(src);
+    } else if constexpr (PB == 4) {
+        *reinterpret_cast<uint32_t *>(dst) = *reinterpret_cast<const uint32_t *>(src);
+    } else if constexpr (PB == 8) {
+        *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
+    } else {
+        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+    }
+}
+
+// Any scale: a thread owns PPX adjacent output columns (each with its own
+// taps) and walks the source rows its strip of output rows reads, in order.
+// Each source row is filtered once into ring slot (row - first row) mod K;
+// an output row is emitted as soon as its last tap row has been filtered,
+// reading its K rows from slots that are constants of the 4-row unrolled
+// walk. The PPX*K tap pixels of the row PD rows ahead are requested before
+// the current row is filtered.
 template <int FILTER, typename T, int C, int PPX>
 struct StripBody {
     using TP = Taps<FILTER>;
     static constexpr int K = TP::K;
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int ROWB = PPX * K * PB;       // tap bytes per source row
+    static constexpr int PD = ROWB <= 32 ? 3 : 1;   // prefetch distance in rows
+    static constexpr int Q = PD + 1;                // divides 4
+    using Raw = RawBuf<ROWB, PB>;
 
-    int32_t ix[PPX][K];
+    int32_t ixb[PPX][K];  // byte offsets of the clamped tap columns
     float wx[PPX][K];
     float ring[K][PPX][C];
+    Raw rawq[Q];
 
-    __device__ __forceinline__ void hrow(const ResizeArgs &a, const unsigned char *src, int32_t r,
-                                         float (&out)[PPX][C])
+    __device__ __forceinline__ Raw load_row(const ResizeArgs &a, const unsigned char *src,
+                                            int32_t r) const
     {
-        const int32_t rr = clampi(r, 0, a.in_h - 1) - a.src_row0;
+        // clamped into the stored band (which holds every needed row)
+        const int32_t rr = clampi(r, a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
         const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
+        Raw raw;
+#pragma unroll
+        for (int c = 0; c < PPX; ++c)
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                copy_pixel<PB>(raw.b + (c * K + i) * PB, row + ixb[c][i]);
+        return raw;
+    }
+
+    __device__ __forceinline__ void hfilter(const Raw &raw, float (&out)[PPX][C]) const
+    {
 #pragma unroll
         for (int c = 0; c < PPX; ++c) {
             float p[C];
-            Pix<T, C>::load(row, ix[c][0], p);
+            decode<T, C>(raw.b, c * K, p);
             fma_first(out[c], wx[c][0], p);
 #pragma unroll
             for (int i = 1; i < K; ++i) {
-                Pix<T, C>::load(row, ix[c][i], p);
+                decode<T, C>(raw.b, c * K + i, p);
                 fma_next(out[c], wx[c][i], p);
             }
         }
@@ -160,48 +202,63 @@ struct StripBody {
             weights<FILTER>(t, u, wx[c]);
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                ix[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
+                ixb[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1) * PB;
         }
         const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
         unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
         const int32_t ncols = min(PPX, a.out_w - col0);
-        int32_t ring_lo = -0x20000000;  // forces a full refill on the first row
-        for (int32_t py = r_begin; py < r_end; ++py) {
-            int32_t y0;
-            float ty, uy;
-            axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty, uy);
-            float wy[K];
-            weights<FILTER>(ty, uy, wy);
-            const int32_t lo = y0 + TP::LO;
-            if (lo - ring_lo >= K) {
+
+        int32_t y = a.dst_row0 + r_begin;  // next output row to emit (logical)
+        const int32_t y_end = a.dst_row0 + r_end;
+        int32_t y0, y0_last;
+        float ty, uy, tl, ul;
+        axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+        axis_tap(y_end - 1, a.in_h, a.out_h, y0_last, tl, ul);
+        float wy[K];
+        weights<FILTER>(ty, uy, wy);
+        int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
+        const int32_t rho0 = y0 + TP::LO;
+        const int32_t rho1 = y0_last + TP::LO + K - 1;
+
+        // emit every output row whose last tap row is rho (ring slot I of rho)
+        auto emit_all = [&](auto slot_tag, int32_t rho) {
+            constexpr int I = decltype(slot_tag)::value;
+            while (y < y_end && last == rho) {
+                unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
 #pragma unroll
-                for (int j = 0; j < K; ++j)
-                    hrow(a, src, lo + j, ring[j]);
-                ring_lo = lo;
-            } else {
-                while (ring_lo < lo) {
+                for (int c = 0; c < PPX; ++c) {
+                    float v[C];
+                    fma_first(v, wy[0], ring[(I + 1) % K][c]);
 #pragma unroll
-                    for (int j = 0; j + 1 < K; ++j)
-#pragma unroll
-                        for (int c = 0; c < PPX; ++c)
-#pragma unroll
-                            for (int ch = 0; ch < C; ++ch)
-                                ring[j][c][ch] = ring[j + 1][c][ch];
-                    hrow(a, src, ring_lo + K, ring[K - 1]);
-                    ++ring_lo;
+                    for (int j = 1; j < K; ++j)
+                        fma_next(v, wy[j], ring[(I + 1 + j) % K][c]);
+                    if (c < ncols)
+                        Pix<T, C>::store(drow, col0 + c, v);
+                }
+                ++y;
+                if (y < y_end) {
+                    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+                    weights<FILTER>(ty, uy, wy);
+                    last = y0 + TP::LO + K - 1;
                 }
             }
-            unsigned char *drow = dst + static_cast<int64_t>(py) * a.dst_pitch;
-#pragma unroll
-            for (int c = 0; c < PPX; ++c) {
-                float v[C];
-                fma_first(v, wy[0], ring[0][c]);
-#pragma unroll
-                for (int j = 1; j < K; ++j)
-                    fma_next(v, wy[j], ring[j][c]);
-                if (c < ncols)
-                    Pix<T, C>::store(drow, col0 + c, v);
+        };
+        auto step = [&](auto slot_tag, int32_t rho) {
+            constexpr int I = decltype(slot_tag)::value;
+            rawq[(I + PD) % Q] = load_row(a, src, rho + PD);
+            if (rho <= rho1) {
+                hfilter(rawq[I % Q], ring[I % K]);
+                emit_all(slot_tag, rho);
             }
+        };
+#pragma unroll
+        for (int i = 0; i < PD; ++i)
+            rawq[i % Q] = load_row(a, src, rho0 + i);
+        for (int32_t rho = rho0; rho <= rho1; rho += 4) {
+            step(std::integral_constant<int, 0>{}, rho);
+            step(std::integral_constant<int, 1>{}, rho + 1);
+            step(std::integral_constant<int, 2>{}, rho + 2);
+            step(std::integral_constant<int, 3>{}, rho + 3);
         }
     }
 };
@@ -252,23 +309,6 @@ __global__ void __launch_bounds__(512) k_strip(ResizeArgs a, int32_t strip_h, in
 // ---------------------------------------------------------------------------
 // k_strip_up2 (exact x2 upscale on both axes)
 // ---------------------------------------------------------------------------
-
-// Copy one pixel of PB bytes between PB-aligned addresses.
-template <int PB>
-__device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned char *src)
-{
-    if constexpr (PB == 1) {
-        *dst = *src;
-    } else if constexpr (PB == 2) {
-        *reinterpret_cast<uint16_t *>(dst) = *reinterpret_cast<const uint16_t *>(src);
-    } else if constexpr (PB == 4) {
-        *reinterpret_cast<uint32_t *>(dst) = *reinterpret_cast<const uint32_t *>(src);
-    } else if constexpr (PB == 8) {
-        *reinterpret_cast<uint2 *>(dst) = *reinterpret_cast<const uint2 *>(src);
-    } else {
-        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
-    }
-}
 
 // Encode N pixels into a byte buffer (uint8 pixels four to a dword).
 template <typename T, int C, int N, int BYTES, int ALIGN>
