@@ -146,7 +146,8 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
  *
  * xr_batch_workspace_bytes(n): bytes of device workspace for n jobs.
  * xr_batch_prepare: validates every job exactly like xr_resize_*, splits
- *   every output into tiles of `tile` (NULL = default shape), orders the jobs
+ *   every output into tiles of `tile` (NULL = the shape xr_batch_autotune
+ *   chose for this dtype, else 256x1 threads with 14-row strips), orders the jobs
  *   largest-first, and uploads the job table and tile prefix sums to
  *   `dev_ws` (device memory, 256-byte aligned, >= xr_batch_workspace_bytes(n))
  *   with an asynchronous copy on `stream`. The host copy of `jobs` may be
@@ -168,6 +169,23 @@ size_t xr_batch_workspace_bytes(int32_t n_jobs);
 int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *dev_ws,
                      size_t ws_bytes, void *stream);
 int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
+
+/*
+ * Autotuner of the batched launch (the paper's tile-shape question, sections
+ * III.A and IV, asked for a whole batch): prepares `dev_ws` with each
+ * candidate shape in turn (NULL = built-in list: 64x4, 128x2 and 256x1
+ * threads, strips of 4 to 46 rows; ppt_x is always 4), times `groups` groups
+ * of `reps` launches with HIP events on `stream`, and keeps the shape with
+ * the smallest median time per launch. On return `dev_ws` is prepared with
+ * that shape, *best / *best_ms (either may be NULL) hold it, and later
+ * xr_batch_prepare calls with tile = NULL and the same dtype use it.
+ * Every timed launch writes every dst (the results do not depend on the
+ * shape). Synchronises `stream`; NOT capturable (XR_ERR_CAPTURE). Errors as
+ * xr_batch_prepare, plus XR_ERR_ARG for reps, groups or candidates < 1.
+ */
+int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candidates,
+                      int32_t n_candidates, int32_t reps, int32_t groups, void *dev_ws,
+                      size_t ws_bytes, xr_tile *best, float *best_ms, void *stream);
 
 /*
  * Adjoint of the resize with respect to its input: grad_src = A^T grad_dst,

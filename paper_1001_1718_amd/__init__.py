@@ -185,6 +185,8 @@ class Batch:
         self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.workspace.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        self._jobs = jobs
         self._keep = pairs
         check(lib.xr_batch_prepare(jobs, self.n, _tile_ptr(tile), ctypes.c_void_p(self.ws_ptr),
                                    nbytes, _stream_handle(pairs[0][0], stream)), "batch_prepare")
@@ -192,6 +194,21 @@ class Batch:
     def run(self, stream=None):
         check(lib.xr_resize_batched(ctypes.c_void_p(self.ws_ptr), self.n,
                                     _stream_handle(self.workspace, stream)), "resize_batched")
+
+    def autotune(self, candidates=None, reps: int = 3, groups: int = 3, stream=None):
+        """Time batched launch shapes (xr_batch_autotune); re-prepares this
+        batch with the fastest and returns (XrTile, ms per launch)."""
+        best, ms = XrTile(), ctypes.c_float()
+        if candidates is None:
+            cand_ptr, nc = None, 0
+        else:
+            cand_ptr = (XrTile * len(candidates))(*candidates)
+            nc = len(candidates)
+        check(lib.xr_batch_autotune(self._jobs, self.n, cand_ptr, nc, reps, groups,
+                                    ctypes.c_void_p(self.ws_ptr), self.ws_bytes, ctypes.byref(best),
+                                    ctypes.byref(ms), _stream_handle(self.workspace, stream)),
+              "batch_autotune")
+        return best, float(ms.value)
 
 
 def autotune(src, dst, mode="bicubic", layout="hwc", candidates=None, reps: int = 20,

@@ -1,6 +1,9 @@
 """Build libxresize.so (gfx950) in-tree with hipcc.
 
-Usage: python -m paper_1001_1718_amd.build_lib   (always recompiles)
+Usage: python paper_1001_1718_amd/build_lib.py   (always recompiles)
+
+Run it as a file, not as `-m paper_1001_1718_amd.build_lib`: importing the
+package loads the library this script builds.
 """
 
 from __future__ import annotations

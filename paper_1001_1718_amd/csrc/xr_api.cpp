@@ -333,6 +333,17 @@ struct BatchInfo {
 };
 std::mutex g_batch_mu;
 std::map<const void *, BatchInfo> g_batches;
+std::map<int32_t, xr_tile> g_batch_tuned;  // dtype -> shape chosen by xr_batch_autotune
+
+// Untuned batched shape: 256-wide workgroups, 14-row strips.
+xr_tile batch_default_tile(int32_t dtype)
+{
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    auto it = g_batch_tuned.find(dtype);
+    if (it != g_batch_tuned.end())
+        return it->second;
+    return xr_tile{XR_KERNEL_STRIP, 256, 1, xr::kBatchPpx, 14, 0};
+}
 
 }  // namespace
 
@@ -369,20 +380,20 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     if (ws_bytes < xr_batch_workspace_bytes(n_jobs))
         return fail(XR_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
                     xr_batch_workspace_bytes(n_jobs));
+    const int32_t dtype = jobs[0].src.dtype;
     xr_tile t{};
     if (tile && tile->kernel != XR_KERNEL_AUTO) {
         t = *tile;
         if (t.kernel != XR_KERNEL_STRIP)
             return fail(XR_ERR_ARG, "the batched launch takes a strip tile");
     } else {
-        t = xr_tile{XR_KERNEL_STRIP, 64, 4, xr::kBatchPpx, 8, 0};
+        t = batch_default_tile(dtype);
     }
     t.ppt_x = xr::kBatchPpx;
     if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256 ||
         t.ppt_y < 1 || t.ppt_y > 4096)
         return fail(XR_ERR_ARG, "batched tile block %dx%d ppt_y %d invalid", t.block_w, t.block_h,
                     t.ppt_y);
-    const int32_t dtype = jobs[0].src.dtype;
     for (int32_t k = 0; k < n_jobs; ++k) {
         const int rc = check_pair(&jobs[k].src, &jobs[k].dst, jobs[k].filter);
         if (rc)
@@ -479,6 +490,98 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream)
                                             static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "batched launch");
+    return XR_OK;
+}
+
+int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candidates,
+                      int32_t n_candidates, int32_t reps, int32_t groups, void *dev_ws,
+                      size_t ws_bytes, xr_tile *best, float *best_ms, void *stream)
+{
+    if (!jobs)
+        return fail(XR_ERR_NULL, "jobs is NULL");
+    if (n_jobs < 1)
+        return fail(XR_ERR_ARG, "n_jobs = %d (must be >= 1)", n_jobs);
+    if (reps < 1 || groups < 1)
+        return fail(XR_ERR_ARG, "reps = %d, groups = %d (both must be >= 1)", reps, groups);
+    std::vector<xr_tile> cand;
+    if (candidates) {
+        if (n_candidates < 1)
+            return fail(XR_ERR_ARG, "n_candidates = %d", n_candidates);
+        cand.assign(candidates, candidates + n_candidates);
+    } else {
+        const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}};
+        const int ppy_list[] = {4, 8, 14, 22, 30, 46};
+        for (const auto &b : blocks)
+            for (int ppy : ppy_list)
+                cand.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], xr::kBatchPpx, ppy, 0});
+    }
+    for (size_t k = 0; k < cand.size(); ++k)
+        if (cand[k].kernel != XR_KERNEL_STRIP)
+            return fail(XR_ERR_ARG, "candidate %zu is not a strip tile", k);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    // validates the jobs, the workspace and the capture state once
+    int rc = xr_batch_prepare(jobs, n_jobs, &cand[0], dev_ws, ws_bytes, stream);
+    if (rc)
+        return rc;
+    hipEvent_t ev0, ev1;
+    hipError_t e = hipEventCreate(&ev0);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipEventCreate");
+    if ((e = hipEventCreate(&ev1)) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        return fail_hip(e, "hipEventCreate");
+    }
+    std::vector<float> per_group(groups);
+    float best_t = 0.0f;
+    size_t best_k = 0;
+    bool have = false;
+    for (size_t k = 0; k < cand.size() && rc == XR_OK && e == hipSuccess; ++k) {
+        rc = xr_batch_prepare(jobs, n_jobs, &cand[k], dev_ws, ws_bytes, stream);
+        if (rc)
+            break;
+        rc = xr_resize_batched(dev_ws, n_jobs, stream);  // warm-up
+        for (int32_t g = 0; g < groups && rc == XR_OK && e == hipSuccess; ++g) {
+            e = hipEventRecord(ev0, s);
+            for (int32_t r = 0; r < reps && rc == XR_OK && e == hipSuccess; ++r)
+                rc = xr_resize_batched(dev_ws, n_jobs, stream);
+            if (rc == XR_OK && e == hipSuccess)
+                e = hipEventRecord(ev1, s);
+            if (rc == XR_OK && e == hipSuccess)
+                e = hipEventSynchronize(ev1);
+            float ms = 0.0f;
+            if (rc == XR_OK && e == hipSuccess)
+                e = hipEventElapsedTime(&ms, ev0, ev1);
+            per_group[g] = ms / static_cast<float>(reps);
+        }
+        if (rc != XR_OK || e != hipSuccess)
+            break;
+        std::sort(per_group.begin(), per_group.end());
+        const float med = per_group[groups / 2];
+        if (!have || med < best_t) {
+            best_t = med;
+            best_k = k;
+            have = true;
+        }
+    }
+    (void)hipEventDestroy(ev0);
+    (void)hipEventDestroy(ev1);
+    if (rc)
+        return rc;
+    if (e != hipSuccess)
+        return fail_hip(e, "timing a candidate");
+    rc = xr_batch_prepare(jobs, n_jobs, &cand[best_k], dev_ws, ws_bytes, stream);
+    if (rc)
+        return rc;
+    {
+        std::lock_guard<std::mutex> lock(g_batch_mu);
+        g_batch_tuned[jobs[0].src.dtype] = cand[best_k];
+    }
+    if (best) {
+        *best = cand[best_k];
+        best->ppt_x = xr::kBatchPpx;
+    }
+    if (best_ms)
+        *best_ms = best_t;
     return XR_OK;
 }
 

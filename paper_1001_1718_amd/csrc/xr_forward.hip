@@ -243,9 +243,11 @@ struct StripBody {
                 }
             }
         };
+        // Requests past the last needed row re-read that row (a cache hit)
+        // instead of fetching rows this strip never uses.
         auto step = [&](auto slot_tag, int32_t rho) {
             constexpr int I = decltype(slot_tag)::value;
-            rawq[(I + PD) % Q] = load_row(a, src, rho + PD);
+            rawq[(I + PD) % Q] = load_row(a, src, min(rho + PD, rho1));
             if (rho <= rho1) {
                 hfilter(rawq[I % Q], ring[I % K]);
                 emit_all(slot_tag, rho);
@@ -253,7 +255,7 @@ struct StripBody {
         };
 #pragma unroll
         for (int i = 0; i < PD; ++i)
-            rawq[i % Q] = load_row(a, src, rho0 + i);
+            rawq[i % Q] = load_row(a, src, min(rho0 + i, rho1));
         for (int32_t rho = rho0; rho <= rho1; rho += 4) {
             step(std::integral_constant<int, 0>{}, rho);
             step(std::integral_constant<int, 1>{}, rho + 1);
@@ -350,6 +352,7 @@ struct Up2Walk {
     const unsigned char *src;
     unsigned char *dst;
     int32_t col0, run0, y_b, y_e;
+    int32_t r_last;  // last source row an emitted output row reads
     float we[K], wo[K];
     // Source row r_first + i sits in ring slot i % K once filtered, and its raw
     // bytes in queue slot i % Q from the time it is requested (PD rows ahead
@@ -441,7 +444,7 @@ struct Up2Walk {
     template <int I>
     __device__ __forceinline__ void step(int32_t r)
     {
-        rawq[(I + PD) % Q] = load_row(r + PD);
+        rawq[(I + PD) % Q] = load_row(min(r + PD, r_last));
         hfilter(rawq[I % Q], ring[I % K]);
         const int32_t y_odd = 2 * r - K + 1;
         if (y_odd >= y_b && y_odd < y_e)
@@ -454,16 +457,19 @@ struct Up2Walk {
     {
         // rows r_min .. r_max produce the output rows [y_b, y_e); the walk
         // runs in groups of 4 rows, so up to 3 rows past r_max are filtered
-        // without emitting anything
+        // (copies of row r_max) without emitting anything
         const int32_t r_min = (y_b + K - 2 + 1) >> 1;  // ceil((y_b + K - 2) / 2), y_b >= 0
         const int32_t r_max = (y_e - 1 + K - 1) >> 1;  // floor((y_e - 1 + K - 1) / 2)
         const int32_t r_first = r_min - K + 1;
+        // requests past r_max re-read row r_max (a cache hit) instead of
+        // fetching rows this strip never uses
+        r_last = r_max;
 #pragma unroll
         for (int i = 0; i < PD; ++i)
-            rawq[i % Q] = load_row(r_first + i);
+            rawq[i % Q] = load_row(min(r_first + i, r_last));
 #pragma unroll
         for (int i = 0; i + 1 < K; ++i) {  // rows r_first .. r_min - 1
-            rawq[(i + PD) % Q] = load_row(r_first + i + PD);
+            rawq[(i + PD) % Q] = load_row(min(r_first + i + PD, r_last));
             hfilter(rawq[i % Q], ring[i % K]);
         }
         for (int32_t r = r_min; r <= r_max; r += 4) {

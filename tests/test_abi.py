@@ -153,6 +153,17 @@ def test_batch_validation():
     assert lib.xr_batch_prepare(jobs, 2, None, None, need, None) == 8
     assert lib.xr_batch_prepare(jobs, 2, None, ws + 8, need, None) == 8
     assert lib.xr_batch_prepare(jobs, 2, None, ws, need - 1, None) == 8
+    # the batch autotuner validates before any HIP call
+    tune = lib.xr_batch_autotune
+    assert tune(None, 2, None, 0, 3, 3, ws, need, None, None, None) == 1
+    assert tune(jobs, 0, None, 0, 3, 3, ws, need, None, None, None) == 11
+    assert tune(jobs, 2, None, 0, 0, 3, ws, need, None, None, None) == 11
+    assert tune(jobs, 2, None, 0, 3, 0, ws, need, None, None, None) == 11
+    gather = (_lib.XrTile * 1)(_lib.tile(_lib.XR_KERNEL_GATHER, 8, 8))
+    assert tune(jobs, 2, gather, 1, 3, 3, ws, need, None, None, None) == 11
+    strip = (_lib.XrTile * 1)(_lib.tile(_lib.XR_KERNEL_STRIP, 256, 1, 4, 14))
+    assert tune(jobs, 2, strip, 0, 3, 3, ws, need, None, None, None) == 11
+    assert tune(jobs, 2, strip, 1, 3, 3, None, need, None, None, None) == 8
     jobs[1].filter = 4
     assert lib.xr_batch_prepare(jobs, 2, None, ws, need, None) == 11
     jobs[1].filter = 1

@@ -114,6 +114,30 @@ def test_full_batch_bitwise_equal_to_per_image():
         compare(got[None], s.cpu().numpy(), j.out_h, j.out_w, f, rows=rows, what=f"job {k}")
 
 
+def test_batch_autotune_picks_a_candidate_and_keeps_results():
+    jobs, pairs = _make_batch(seed=3, count=24, side_hi=512, content="field")
+    ref = _per_image(pairs)
+    b = xr.Batch(pairs)
+    cands = [xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 4, 8), xr.tile(xr.XR_KERNEL_STRIP, 256, 1, 4, 14),
+             xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 4, 30)]
+    best, ms = b.autotune(candidates=cands, reps=2, groups=3)
+    assert ms > 0 and best.as_tuple() in [c.as_tuple() for c in cands]
+    for _, d, _ in pairs:
+        d.zero_()
+    b.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
+    # the built-in candidate list, then a batch prepared with the tuned default
+    best, ms = b.autotune(reps=1, groups=1)
+    assert ms > 0 and best.kernel == xr.XR_KERNEL_STRIP and best.ppt_x == 4
+    b2 = xr.Batch(pairs)
+    for _, d, _ in pairs:
+        d.zero_()
+    b2.run()
+    torch.cuda.synchronize()
+    assert all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
+
+
 def test_prepare_validation():
     s = torch.zeros((8, 8, 1), dtype=torch.uint8, device=DEV)
     d = torch.zeros((16, 16, 1), dtype=torch.uint8, device=DEV)
