@@ -127,7 +127,7 @@ def headline(args, torch, xr, fields):
                     xr.tile(*(int(v) for v in args.tile.split(","))))
     elif not args.no_tune:
         cands = [c for c in xr.tune_candidates("bicubic", xr.XR_U8, ch, in_hw, in_hw, out_hw, out_hw)
-                 if c.kernel == xr.XR_KERNEL_STRIP]
+                 if c.kernel in (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS)]
         t0 = time.perf_counter()
         tile, best_ms = xr.autotune(srcs, dsts, "bicubic", candidates=cands, reps=8, groups=3)
         tune = {"candidates": len(cands), "seconds": round(time.perf_counter() - t0, 2),
@@ -325,8 +325,12 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         srcs = [src0] + [src0.clone() for _ in range(n_buf - 1)]
         dsts = [torch.empty(out_shape, dtype=src0.dtype, device=dev) for _ in range(n_buf)]
 
-        cands = [c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], src0.shape[-1] if layout == "hwc" and src0.dim() == 3 else 1,
-                                               1, 1, 1, 1) if c.kernel == xr.XR_KERNEL_STRIP]
+        chans = src0.shape[-1] if layout == "hwc" and src0.dim() == 3 else 1
+        in_hw = src0.shape[:2] if layout == "hwc" else src0.shape[-2:]
+        out_hw = out_shape[:2] if layout == "hwc" else out_shape[-2:]
+        cands = [c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], chans, in_hw[1], in_hw[0],
+                                               out_hw[1], out_hw[0])
+                 if c.kernel in (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS)]
         tile, _ = xr.autotune(srcs, dsts, mode, layout=layout, candidates=cands, reps=4, groups=3)
 
         def launch(i):

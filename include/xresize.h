@@ -101,6 +101,13 @@ typedef struct {
  *                               on both axes runs a variant specialised for it.
  *         = XR_KERNEL_STRIP_ANY : the strip kernel without the x2 variant (the
  *                               same results; for comparisons)
+ *         = XR_KERNEL_STRIP_LDS : the strip walk with each source row staged
+ *                               once per workgroup in LDS, taps read from LDS
+ *                               (any scale; block_h = 1, block_w a multiple of
+ *                               64 up to 512, ppt_x = 4 for 4 channels and 8
+ *                               for one). XR_ERR_ARG when one workgroup's row
+ *                               segment does not fit its LDS budget (strong
+ *                               downscales with wide workgroups)
  *  order  = 0 : tiles are processed in launch order (row-major)
  *         = 1 : the launch is split into 8 contiguous bands of tiles, one per
  *               XCD (the hardware deals workgroups to the 8 XCDs in turn), so
@@ -110,6 +117,7 @@ typedef struct {
 #define XR_KERNEL_GATHER 1
 #define XR_KERNEL_STRIP 2
 #define XR_KERNEL_STRIP_ANY 3
+#define XR_KERNEL_STRIP_LDS 4
 
 typedef struct {
     int32_t kernel;

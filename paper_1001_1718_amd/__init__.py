@@ -24,6 +24,7 @@ from ._lib import (  # noqa: F401
     XR_KERNEL_GATHER,
     XR_KERNEL_STRIP,
     XR_KERNEL_STRIP_ANY,
+    XR_KERNEL_STRIP_LDS,
     XR_U8,
     XResizeError,
     XrImage,

@@ -29,7 +29,7 @@ XR_ERR_ARG = 11
 XR_U8, XR_F16, XR_F32 = 0, 1, 2
 XR_BILINEAR, XR_BICUBIC = 0, 1
 XR_MAX_SIDE = 32768
-XR_KERNEL_AUTO, XR_KERNEL_GATHER, XR_KERNEL_STRIP, XR_KERNEL_STRIP_ANY = 0, 1, 2, 3
+XR_KERNEL_AUTO, XR_KERNEL_GATHER, XR_KERNEL_STRIP, XR_KERNEL_STRIP_ANY, XR_KERNEL_STRIP_LDS = 0, 1, 2, 3, 4
 
 
 class XrImage(ctypes.Structure):
@@ -61,7 +61,7 @@ class XrTile(ctypes.Structure):
         return (self.kernel, self.block_w, self.block_h, self.ppt_x, self.ppt_y, self.order)
 
     def __repr__(self):
-        kind = {0: "auto", 1: "gather", 2: "strip", 3: "strip_any"}.get(self.kernel, str(self.kernel))
+        kind = {0: "auto", 1: "gather", 2: "strip", 3: "strip_any", 4: "strip_lds"}.get(self.kernel, str(self.kernel))
         return (f"XrTile({kind}, block={self.block_w}x{self.block_h}, "
                 f"ppt={self.ppt_x}x{self.ppt_y}, order={self.order})")
 

@@ -163,6 +163,15 @@ int check_pair(const xr_image *src, const xr_image *dst, int32_t filter)
     return XR_OK;
 }
 
+// The source base and pitches are 4-byte aligned and a row is a whole number
+// of 4-byte words (the LDS strip kernel then stages small pixels as words).
+bool src_aligned4(const xr_image &src)
+{
+    const int64_t row_bytes = static_cast<int64_t>(src.width) * src.channels * elem_size(src.dtype);
+    return reinterpret_cast<uintptr_t>(src.data) % 4 == 0 && src.row_pitch % 4 == 0 &&
+           (src.planes == 1 || src.plane_pitch % 4 == 0) && row_bytes % 4 == 0;
+}
+
 xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
 {
     xr::ResizeArgs a{};
@@ -185,6 +194,7 @@ xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
         return reinterpret_cast<uintptr_t>(p) % 16 == 0 && v1 % 16 == 0 && v2 % 16 == 0;
     };
     a.aligned16 = al(src.data, a.src_pitch, a.src_plane_pitch) && al(dst.data, a.dst_pitch, a.dst_plane_pitch);
+    a.aligned4 = src_aligned4(src);
     return a;
 }
 
@@ -276,7 +286,45 @@ int check_tile(const xr_tile &t, int32_t dtype, int32_t channels)
             return fail(XR_ERR_ARG, "strip ppt_y = %d outside 1..4096", t.ppt_y);
         return XR_OK;
     }
+    if (t.kernel == XR_KERNEL_STRIP_LDS) {
+        if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_w > 512 || t.block_h != 1)
+            return fail(XR_ERR_ARG,
+                        "LDS strip tile block %dx%d invalid: block_h 1, block_w a multiple of 64 up to 512",
+                        t.block_w, t.block_h);
+        if (t.order != 0 && t.order != 1)
+            return fail(XR_ERR_ARG, "tile.order = %d (must be 0 or 1)", t.order);
+        const int32_t ppx = xr::kLdsPpx[channels == 4 ? 1 : 0];
+        if (t.ppt_x != ppx)
+            return fail(XR_ERR_ARG, "LDS strip ppt_x = %d (must be %d for %d channels)", t.ppt_x, ppx,
+                        channels);
+        if (t.ppt_y < 1 || t.ppt_y > 4096)
+            return fail(XR_ERR_ARG, "strip ppt_y = %d outside 1..4096", t.ppt_y);
+        (void)dtype;
+        return XR_OK;
+    }
     return fail(XR_ERR_ARG, "tile.kernel = %d unknown", t.kernel);
+}
+
+// The LDS-staged strip kernel stages one workgroup's source row segment; it
+// must fit the kernel's LDS and register budget for this scale.
+// `aligned4` is unknown (taken as true) where only sizes are given.
+int check_lds(const xr_tile &t, int32_t filter, int32_t dtype, int32_t channels, int32_t in_w,
+              int32_t out_w, bool aligned4 = true)
+{
+    if (t.kernel != XR_KERNEL_STRIP_LDS)
+        return XR_OK;
+    if (!xr::strip_lds_fits(filter, dtype, channels, in_w, out_w, t.block_w, aligned4))
+        return fail(XR_ERR_ARG,
+                    "LDS strip: a %d-thread workgroup's row segment for %d -> %d columns does not fit "
+                    "(or one-channel source rows are not 4-byte aligned words); use a narrower "
+                    "workgroup or another kernel", t.block_w, in_w, out_w);
+    return XR_OK;
+}
+
+bool lds_usable(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
+{
+    return xr::strip_lds_fits(filter, src.dtype, src.channels, src.width, dst.width, t.block_w,
+                              src_aligned4(src));
 }
 
 xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, const xr_image &dst)
@@ -287,7 +335,10 @@ xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, c
                                  dst.height);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
-    if (it != g_tuned.end())
+    // a tuned LDS shape applies only to sources it can stage (alignment is
+    // not part of the key)
+    if (it != g_tuned.end() &&
+        (it->second.kernel != XR_KERNEL_STRIP_LDS || lds_usable(it->second, filter, src, dst)))
         return it->second;
     return default_tile(src.channels, dst.width, dst.rows, dst.planes);
 }
@@ -313,6 +364,9 @@ int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile,
     if (rc)
         return rc;
     rc = check_grid(t, *dst);
+    if (rc)
+        return rc;
+    rc = check_lds(t, filter, src->dtype, src->channels, src->width, dst->width, src_aligned4(*src));
     if (rc)
         return rc;
     const xr::ResizeArgs a = make_args(*src, *dst);
@@ -629,10 +683,7 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
 int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w,
                            int32_t in_h, int32_t out_w, int32_t out_h, xr_tile *out, int32_t cap)
 {
-    (void)filter;
-    (void)in_w;
     (void)in_h;
-    (void)out_w;
     (void)out_h;
     std::vector<xr_tile> c;
     // the paper's block shapes (W x H threads, one pixel each) and a few wider ones
@@ -654,6 +705,15 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
             for (int ppy : ppy_list)
                 for (int order = 0; order < 2; ++order)
                     c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, order});
+    }
+    // the LDS-staged walk, where one workgroup's row segment fits
+    const int lds_ppx = xr::kLdsPpx[channels == 4 ? 1 : 0];
+    for (int bw : {64, 128, 256, 512}) {
+        if (!xr::strip_lds_fits(filter, dtype, channels, in_w, out_w, bw, true))
+            continue;
+        for (int ppy : ppy_list)
+            for (int order = 0; order < 2; ++order)
+                c.push_back(xr_tile{XR_KERNEL_STRIP_LDS, bw, 1, lds_ppx, ppy, order});
     }
     if (out)
         for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)
@@ -695,6 +755,15 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         cand.resize(n);
         xr_tune_candidates(filter, src->dtype, src->channels, src->width, src->height, dst->width,
                            dst->height, cand.data(), n);
+        // the built-in list assumes aligned sources; drop the LDS shapes
+        // these sources cannot use
+        for (int32_t k = 0; k < n_pairs; ++k)
+            cand.erase(std::remove_if(cand.begin(), cand.end(),
+                                      [&](const xr_tile &t) {
+                                          return t.kernel == XR_KERNEL_STRIP_LDS &&
+                                                 !lds_usable(t, filter, srcs[k], dsts[k]);
+                                      }),
+                       cand.end());
     }
     for (size_t k = 0; k < cand.size(); ++k) {
         if (cand[k].kernel == XR_KERNEL_AUTO)
@@ -702,6 +771,9 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         rc = check_tile(cand[k], src->dtype, src->channels);
         if (!rc)
             rc = check_grid(cand[k], *dst);
+        if (!rc)
+            rc = check_lds(cand[k], filter, src->dtype, src->channels, src->width, dst->width,
+                           std::all_of(srcs, srcs + n_pairs, [](const xr_image &i) { return src_aligned4(i); }));
         if (rc)
             return fail(rc, "candidate %zu: %s", k, g_last_error.c_str());
     }
@@ -814,7 +886,9 @@ int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
         g_tuned.erase(key);
         return XR_OK;
     }
-    const int rc = check_tile(*tile, dtype, channels);
+    int rc = check_tile(*tile, dtype, channels);
+    if (!rc)
+        rc = check_lds(*tile, filter, dtype, channels, in_w, out_w);
     if (rc)
         return rc;
     g_tuned[key] = *tile;

@@ -20,6 +20,7 @@
 // (xr_device.hpp), so their results are bit-identical.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "xr_device.hpp"
@@ -306,6 +307,195 @@ __global__ void __launch_bounds__(512) k_strip(ResizeArgs a, int32_t strip_h, in
     const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
     StripBody<FILTER, T, C, PPX> body;
     body.run(a, blockIdx.z, col0, r_begin, r_end);
+}
+
+// ---------------------------------------------------------------------------
+// k_strip_lds (any scale, each source row staged once per workgroup in LDS)
+// ---------------------------------------------------------------------------
+
+// Staging plan of the LDS strip walk. A lane moves CB-byte chunks: whole
+// pixels of 4 bytes or more, else aligned 4-byte words (which needs a 4-byte
+// aligned source with rows of a whole number of words). One workgroup of bw
+// threads covers cols = min(bw * PPX, out_w) output columns and reads a
+// segment of at most seg_max = floor((cols - 1) * in_w / out_w) + K + 1
+// source pixels,
+// since x0(c2) - x0(c1) <= floor((c2 - c1) * in_w / out_w) + 1 (eqs. 1-4);
+// with the word alignment slack that is at most `chunks` chunks, `need`
+// chunks per lane, in an LDS row buffer of `buf_bytes`.
+template <int FILTER, typename T, int C, int PPX>
+struct LdsPlan {
+    static constexpr int K = Taps<FILTER>::K;
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int CB = PB < 4 ? 4 : PB;
+    static constexpr int MAX_CH = 64 / CB;  // registers for one row's chunks
+    int64_t chunks, need, buf_bytes;
+    bool ok;
+    LdsPlan(int32_t in_w, int32_t out_w, int32_t bw, bool aligned4)
+    {
+        const int64_t cols = std::min<int64_t>(static_cast<int64_t>(bw) * PPX, out_w);
+        const int64_t seg = (cols - 1) * in_w / out_w + K + 1;
+        chunks = (seg * PB + (CB - PB) + CB - 1) / CB;
+        need = (chunks + bw - 1) / bw;
+        buf_bytes = (chunks * CB + 15) / 16 * 16;
+        ok = need <= MAX_CH && 3 * buf_bytes <= static_cast<int64_t>(kLdsBudget) &&
+             (PB >= 4 || aligned4);
+    }
+};
+
+// The workgroup is one row strip (block_h = 1): all its threads read the same
+// source rows. Per source row, every lane loads CH chunks of the row segment
+// (coalesced, clamped into the segment, so the loads are unconditional) and
+// writes them to one of three LDS row buffers; after one barrier per row each
+// thread gathers its PPX * K taps from LDS, filters them into its ring, and
+// emits output rows exactly like k_strip (same weights, same order). Row
+// rho + 1 is written to LDS while row rho is filtered; row rho + 2 is in
+// flight from memory meanwhile. Every thread of the workgroup runs the same
+// loop and barrier sequence (the strip and trip count are uniform; threads
+// past the right edge only skip their stores).
+template <int FILTER, typename T, int C, int PPX, int CH>
+__global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h, int32_t order,
+                                                   int32_t buf_bytes)
+{
+    using TP = Taps<FILTER>;
+    constexpr int K = TP::K;
+    constexpr int PB = Pix<T, C>::kBytes;
+    constexpr int CB = PB < 4 ? 4 : PB;
+    using Chunk = RawBuf<CB, CB>;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+
+    int32_t bx, by;
+    tile_coords(order, bx, by);
+    const int32_t bw = static_cast<int32_t>(blockDim.x);
+    const int32_t tid = static_cast<int32_t>(threadIdx.x);
+    const int32_t c_first = bx * bw * PPX;
+    const int32_t r_begin = by * strip_h;
+    if (c_first >= a.out_w || r_begin >= a.dst_rows)  // uniform over the workgroup
+        return;
+    const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
+    const int32_t col0 = c_first + tid * PPX;
+    const int32_t c_last = min(c_first + bw * PPX - 1, a.out_w - 1);
+
+    // the workgroup's segment of source columns [seg0, seg1], staged from the
+    // chunk-aligned byte seg_b0 on
+    int32_t xa, xb;
+    float tq, uq;
+    axis_tap(c_first, a.in_w, a.out_w, xa, tq, uq);
+    axis_tap(c_last, a.in_w, a.out_w, xb, tq, uq);
+    const int32_t seg0 = clampi(xa + TP::LO, 0, a.in_w - 1);
+    const int32_t seg1 = clampi(xb + TP::LO + K - 1, 0, a.in_w - 1);
+    const int32_t seg_b0 = (seg0 * PB) & ~(CB - 1);
+    const int32_t nch = ((seg1 + 1) * PB - seg_b0 + CB - 1) / CB;
+
+    // this thread's taps, as byte offsets into the staged segment
+    int32_t toff[PPX][K];
+    float wx[PPX][K];
+#pragma unroll
+    for (int c = 0; c < PPX; ++c) {
+        const int32_t x = min(col0 + c, a.out_w - 1);
+        int32_t x0;
+        float t, u;
+        axis_tap(x, a.in_w, a.out_w, x0, t, u);
+        weights<FILTER>(t, u, wx[c]);
+#pragma unroll
+        for (int i = 0; i < K; ++i)
+            toff[c][i] = clampi(x0 + TP::LO + i, 0, a.in_w - 1) * PB - seg_b0;
+    }
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
+    const int32_t ncols = min(PPX, a.out_w - col0);
+
+    int32_t y = a.dst_row0 + r_begin;  // next output row to emit (logical)
+    const int32_t y_end = a.dst_row0 + r_end;
+    int32_t y0, y0_last;
+    float ty, uy, tl, ul;
+    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+    axis_tap(y_end - 1, a.in_h, a.out_h, y0_last, tl, ul);
+    float wy[K];
+    weights<FILTER>(ty, uy, wy);
+    int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
+    const int32_t rho0 = y0 + TP::LO;
+    const int32_t rho1 = y0_last + TP::LO + K - 1;
+
+    Chunk q[CH];
+    // the CH chunks of source row rho (clamped into the band, and to rho1:
+    // requests past the last needed row re-read it) that this lane stages
+    auto fetch = [&](int32_t rho) {
+        const int32_t rr = clampi(min(rho, rho1), a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch + seg_b0;
+#pragma unroll
+        for (int k = 0; k < CH; ++k)
+            q[k] = load_raw<CB, CB>(row + min(tid + k * bw, nch - 1) * CB);
+    };
+    auto stage = [&](int32_t buf) {
+        unsigned char *b = lds + buf * buf_bytes;
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int32_t i = tid + k * bw;
+            if (i < nch)
+                store_raw<CB, CB>(b + i * CB, q[k]);
+        }
+    };
+    float ring[K][PPX][C];
+    auto filter_row = [&](int32_t buf, float (&out)[PPX][C]) {
+        const unsigned char *b = lds + buf * buf_bytes;
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            float p[C];
+            Pix<T, C>::load(b + toff[c][0], 0, p);
+            fma_first(out[c], wx[c][0], p);
+#pragma unroll
+            for (int i = 1; i < K; ++i) {
+                Pix<T, C>::load(b + toff[c][i], 0, p);
+                fma_next(out[c], wx[c][i], p);
+            }
+        }
+    };
+    auto emit_all = [&](auto slot_tag, int32_t rho) {
+        constexpr int I = decltype(slot_tag)::value;
+        while (y < y_end && last == rho) {
+            unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
+#pragma unroll
+            for (int c = 0; c < PPX; ++c) {
+                float v[C];
+                fma_first(v, wy[0], ring[(I + 1) % K][c]);
+#pragma unroll
+                for (int j = 1; j < K; ++j)
+                    fma_next(v, wy[j], ring[(I + 1 + j) % K][c]);
+                if (c < ncols)
+                    Pix<T, C>::store(drow, col0 + c, v);
+            }
+            ++y;
+            if (y < y_end) {
+                axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+                weights<FILTER>(ty, uy, wy);
+                last = y0 + TP::LO + K - 1;
+            }
+        }
+    };
+    // Row rho sits in LDS buffer (rho - rho0) mod 3 and ring slot
+    // (rho - rho0) mod K. Buffer (b + 1) mod 3 was last read two rows ago,
+    // before the previous barrier, so it can be refilled now.
+    auto step = [&](auto slot_tag, int32_t rho) {
+        constexpr int I = decltype(slot_tag)::value;
+        if (rho <= rho1) {  // uniform over the workgroup
+            const int32_t b = (rho - rho0) % 3;
+            stage(b == 2 ? 0 : b + 1);  // row rho + 1
+            fetch(rho + 2);
+            __syncthreads();
+            filter_row(b, ring[I % K]);
+            emit_all(slot_tag, rho);
+        }
+    };
+    fetch(rho0);
+    stage(0);
+    fetch(rho0 + 1);
+    __syncthreads();
+    for (int32_t rho = rho0; rho <= rho1; rho += 4) {
+        step(std::integral_constant<int, 0>{}, rho);
+        step(std::integral_constant<int, 1>{}, rho + 1);
+        step(std::integral_constant<int, 2>{}, rho + 2);
+        step(std::integral_constant<int, 3>{}, rho + 3);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -633,6 +823,40 @@ int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads)
 // dispatch
 // ---------------------------------------------------------------------------
 
+namespace {
+template <int FILTER, typename T, int C>
+bool lds_fits(int32_t in_w, int32_t out_w, int32_t block_w, bool aligned4)
+{
+    return LdsPlan<FILTER, T, C, kLdsPpx[C == 4 ? 1 : 0]>(in_w, out_w, block_w, aligned4).ok;
+}
+template <int FILTER>
+bool lds_fits_filter(int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w, int32_t block_w,
+                     bool aligned4)
+{
+    switch (dtype) {
+    case XR_U8:
+        return channels == 4 ? lds_fits<FILTER, uint8_t, 4>(in_w, out_w, block_w, aligned4)
+                             : lds_fits<FILTER, uint8_t, 1>(in_w, out_w, block_w, aligned4);
+    case XR_F16:
+        return channels == 4 ? lds_fits<FILTER, _Float16, 4>(in_w, out_w, block_w, aligned4)
+                             : lds_fits<FILTER, _Float16, 1>(in_w, out_w, block_w, aligned4);
+    case XR_F32:
+        return channels == 4 ? lds_fits<FILTER, float, 4>(in_w, out_w, block_w, aligned4)
+                             : lds_fits<FILTER, float, 1>(in_w, out_w, block_w, aligned4);
+    default:
+        return false;
+    }
+}
+}  // namespace
+
+bool strip_lds_fits(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w,
+                    int32_t block_w, bool aligned4)
+{
+    return filter == XR_BICUBIC
+               ? lds_fits_filter<kBicubic>(dtype, channels, in_w, out_w, block_w, aligned4)
+               : lds_fits_filter<kBilinear>(dtype, channels, in_w, out_w, block_w, aligned4);
+}
+
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
 {
     (void)dtype;
@@ -644,8 +868,43 @@ bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
 namespace {
 
 template <int FILTER, typename T, int C>
+hipError_t launch_lds(const ResizeArgs &a, const xr_tile &tile, hipStream_t stream)
+{
+    constexpr int PPX = kLdsPpx[C == 4 ? 1 : 0];
+    using Plan = LdsPlan<FILTER, T, C, PPX>;
+    const Plan plan(a.in_w, a.out_w, tile.block_w, a.aligned4 != 0);
+    if (!plan.ok)
+        return hipErrorInvalidValue;
+    const size_t lds = 3 * static_cast<size_t>(plan.buf_bytes);
+    const int32_t buf_bytes = static_cast<int32_t>(plan.buf_bytes);
+    const int32_t cols_per_block = tile.block_w * PPX;
+    const dim3 block(tile.block_w, 1, 1);
+    const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
+                    (a.dst_rows + tile.ppt_y - 1) / tile.ppt_y, a.planes);
+#define XR_LDS_CASE(N)                                                                        \
+    if (plan.need <= N) {                                                                     \
+        hipLaunchKernelGGL((k_strip_lds<FILTER, T, C, PPX, N>), grid, block, lds, stream, a,  \
+                           tile.ppt_y, tile.order, buf_bytes);                                \
+        return hipGetLastError();                                                             \
+    }
+    XR_LDS_CASE(1)
+    XR_LDS_CASE(2)
+    XR_LDS_CASE(4)
+    if constexpr (Plan::MAX_CH >= 8) {
+        XR_LDS_CASE(8)
+    }
+    if constexpr (Plan::MAX_CH >= 16) {
+        XR_LDS_CASE(16)
+    }
+#undef XR_LDS_CASE
+    return hipErrorInvalidValue;
+}
+
+template <int FILTER, typename T, int C>
 hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, hipStream_t stream)
 {
+    if (tile.kernel == XR_KERNEL_STRIP_LDS)
+        return launch_lds<FILTER, T, C>(a, tile, stream);
     if (tile.kernel == XR_KERNEL_GATHER) {
         const dim3 block(tile.block_w, tile.block_h, 1);
         const dim3 grid((a.out_w + tile.block_w - 1) / tile.block_w,

@@ -24,6 +24,8 @@ struct ResizeArgs {
     int32_t dst_rows;        // number of output rows to compute
     int32_t planes;
     int32_t aligned16;       // src, dst and pitches are 16-byte aligned
+    int32_t aligned4;        // src and its pitches are 4-byte aligned and a
+                             // source row is a whole number of 4-byte words
 };
 
 // Entry of the device job table of the batched launch.
@@ -67,6 +69,16 @@ bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels);
 
 // Pixels per thread along x that the strip kernel is instantiated for.
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx);
+// Columns per thread of the LDS-staged strip kernel: {one channel, four}.
+constexpr int32_t kLdsPpx[2] = {8, 4};
+// Dynamic LDS of the LDS-staged strip kernel (three row buffers) is kept
+// within this many bytes per workgroup.
+constexpr size_t kLdsBudget = 64 * 1024;
+// True when a workgroup of block_w threads of the LDS-staged strip kernel can
+// stage its source row segment for an in_w -> out_w resize (`aligned4` as in
+// ResizeArgs; pixels of fewer than 4 bytes are staged as 4-byte words).
+bool strip_lds_fits(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w,
+                    int32_t block_w, bool aligned4);
 // Output columns per thread of the batched kernel (both channel counts).
 constexpr int32_t kBatchPpx = 4;
 

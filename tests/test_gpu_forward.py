@@ -31,6 +31,8 @@ TILES = {
     "strip_any": xr.tile(xr.XR_KERNEL_STRIP_ANY, 128, 2, 0, 5),
     "strip_xcd": xr.tile(xr.XR_KERNEL_STRIP, 512, 1, 0, 9, 1),
     "strip_any_xcd": xr.tile(xr.XR_KERNEL_STRIP_ANY, 64, 2, 0, 3, 1),
+    "strip_lds": xr.tile(xr.XR_KERNEL_STRIP_LDS, 64, 1, 0, 7),
+    "strip_lds_xcd": xr.tile(xr.XR_KERNEL_STRIP_LDS, 256, 1, 0, 3, 1),
 }
 
 
@@ -85,11 +87,57 @@ def test_small_all_kernels(shape, dtype, channels, mode):
     img = _input(dtype, in_h, in_w, channels, seed=in_h * 1000 + in_w + channels)
     outs = {}
     for name in TILES:
-        outs[name] = _gpu(img, out_h, out_w, mode, _tile_for(name, channels))
+        t = _tile_for(name, channels)
+        if name.startswith("strip_lds") and (in_w * channels * np.dtype(dtype).itemsize) % 4:
+            # the LDS walk stages small pixels as 4-byte words: rows that are
+            # not whole words are refused, not read past their end
+            with pytest.raises(xr.XResizeError) as e:
+                _gpu(img, out_h, out_w, mode, t)
+            assert e.value.code == 11
+            continue
+        outs[name] = _gpu(img, out_h, out_w, mode, t)
     compare(outs["auto"], img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
     for name, o in outs.items():
         np.testing.assert_array_equal(o.view(np.uint8), outs["auto"].view(np.uint8),
                                       err_msg=f"kernel {name} differs from the default")
+
+
+LDS_CASES = [
+    ((300, 2201), (97, 1290), np.uint8, 4, 256),     # non-dyadic shrink, several workgroups, ragged
+    ((130, 1537), (290, 4100), np.float32, 1, 128),  # non-dyadic upscale, ragged right edge
+    ((64, 4096), (40, 1024), np.uint8, 1, 256),      # x0.25 across: 16 chunks per lane
+    ((50, 3001), (77, 1801), np.float16, 4, 64),     # ~x0.6, narrow workgroups
+    ((40, 700), (40, 5600), np.float32, 4, 512),     # x8 across: one chunk per lane
+]
+
+
+@pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: f"{c[0][1]}-{c[1][1]}-c{c[3]}-bw{c[4]}")
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_lds_strip_wide_images(case, mode):
+    (in_h, in_w), (out_h, out_w), dtype, channels, bw = case
+    img = _input(dtype, in_h, in_w, channels, seed=in_w + channels)
+    ppx = 4 if channels == 4 else 8
+    lds = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_STRIP_LDS, bw, 1, ppx, 13, 1))
+    ref = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_STRIP_ANY, 64, 1, ppx, 13))
+    np.testing.assert_array_equal(lds.view(np.uint8), ref.view(np.uint8))
+    rng = np.random.default_rng(in_w)
+    rows = np.unique(np.concatenate([[0, out_h - 1], rng.integers(0, out_h, 6)]))
+    compare(lds[rows], img, out_h, out_w, MODES[mode], rows=rows, what=f"LDS {case} {mode}")
+
+
+def test_lds_strip_rejects_what_it_cannot_stage():
+    x = torch.zeros((4, 32768), dtype=torch.float32, device=DEV)
+    with pytest.raises(xr.XResizeError) as e:  # segment beyond the LDS budget
+        xr.resize(x, (4, 64), "bicubic", tile=xr.tile(xr.XR_KERNEL_STRIP_LDS, 512, 1, 8, 4))
+    assert e.value.code == 11
+    u = torch.zeros((8, 37), dtype=torch.uint8, device=DEV)  # rows of 37 bytes: not whole words
+    with pytest.raises(xr.XResizeError) as e:
+        xr.resize(u, (16, 74), "bicubic", tile=xr.tile(xr.XR_KERNEL_STRIP_LDS, 64, 1, 8, 4))
+    assert e.value.code == 11
+    # the default shape never picks what the source cannot use
+    out = xr.resize(u, (16, 74), "bicubic")
+    torch.cuda.synchronize()
+    assert int(out.sum()) == 0
 
 
 @pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
