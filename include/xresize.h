@@ -98,9 +98,10 @@ typedef struct {
  *                               ppt_x columns and reuses the filtered rows
  *                               from registers; block_w a multiple of 64 and
  *                               block_w * block_h <= 512. An exact x2 upscale
- *                               on both axes runs a variant specialised for it.
- *         = XR_KERNEL_STRIP_ANY : the strip kernel without the x2 variant (the
- *                               same results; for comparisons)
+ *                               or x0.5 downscale on both axes runs a variant
+ *                               specialised for it.
+ *         = XR_KERNEL_STRIP_ANY : the strip kernel without the x2 and x0.5
+ *                               variants (the same results; for comparisons)
  *         = XR_KERNEL_STRIP_LDS : the strip walk with each source row staged
  *                               once per workgroup in LDS, taps read from LDS
  *                               (any scale; block_h = 1, block_w a multiple of

@@ -202,7 +202,11 @@ int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t)
 {
     if (t.kernel != XR_KERNEL_STRIP)
         return xr::kGeneral;
-    return (dst.width == 2 * src.width && dst.height == 2 * src.height) ? xr::kUp2 : xr::kGeneral;
+    if (dst.width == 2 * src.width && dst.height == 2 * src.height)
+        return xr::kUp2;
+    if (2 * dst.width == src.width && 2 * dst.height == src.height)
+        return xr::kDown2;
+    return xr::kGeneral;
 }
 
 // ---- launch shapes ------------------------------------------------------

@@ -15,6 +15,10 @@
 //               t = 1/4, a thread's ppt_x columns read one contiguous run of
 //               ppt_x/2 + K source pixels with wide loads, and every source
 //               row produces two output rows.
+//  k_strip_down2  the walk for an exact x0.5 on both axes: t = 1/2
+//               everywhere, a contiguous run of 2 ppt_x - 2 + K source
+//               pixels per row, two source rows per output row.
+//  k_strip_lds  any scale, each source row staged once per workgroup in LDS.
 //
 // All three evaluate each output with the same float32 operation sequence
 // (xr_device.hpp), so their results are bit-identical.
@@ -698,6 +702,175 @@ __global__ void __launch_bounds__(512) k_strip_up2(ResizeArgs a, int32_t strip_h
 }
 
 // ---------------------------------------------------------------------------
+// k_strip_down2 (exact x0.5 on both axes)
+// ---------------------------------------------------------------------------
+
+// For out = in / 2 every output column and row has s = 2x + 1/2: x0 = 2x and
+// t = 1/2, so output x taps source 2x + LO + i with the weights of t = 1/2
+// (bicubic (-1, 9, 9, -1) / 16, bilinear (1/2, 1/2)). A thread's PPX columns
+// read one contiguous run of source pixels; it is loaded from a 16-byte
+// aligned start PAD pixels to the left, so the loads are wide. Every output
+// row reads K source rows starting at 2y + LO: the walk filters two new
+// source rows per output row into a ring of K, unrolled by two output rows
+// (four source rows, a multiple of K and of the prefetch queue) so every
+// slot is a constant. Same float32 evaluation order as the other kernels.
+template <int FILTER, typename T, int C, int PPX, bool WIDE>
+struct Down2Walk {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+    static constexpr int LO = TP::LO;
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int NEED = 2 * PPX - 2 + K;  // source pixels a thread reads per row
+    // alignment of 2 * col0 * PB, capped at 16 bytes
+    static constexpr int RUN_ALIGN = WIDE ? cmin(16, (2 * PPX * PB) & -(2 * PPX * PB)) : PB;
+    static constexpr int U = RUN_ALIGN / PB > 0 ? RUN_ALIGN / PB : 1;  // alignment unit in pixels
+    static constexpr int PAD = WIDE ? ((-LO + U - 1) / U) * U : -LO;   // pixels left of the first tap
+    static constexpr int SPAN = WIDE ? ((PAD + LO + NEED + U - 1) / U) * U : NEED;  // pixels loaded
+    static constexpr int OFF = WIDE ? PAD + LO : 0;  // run index of the first needed pixel
+    static constexpr int OUT_ALIGN = cmin(16, PPX * PB);
+    using Raw = RawBuf<SPAN * PB, WIDE ? RUN_ALIGN : PB>;
+    static constexpr int PD = (SPAN * PB <= 32) ? 3 : 1;  // prefetch distance in rows
+    static constexpr int Q = PD + 1;
+
+    const ResizeArgs &a;
+    const unsigned char *src;
+    unsigned char *dst;
+    int32_t col0, run0, y_b, y_e, r_last;
+    float w[K];
+    float ring[K][PPX][C];
+    Raw rawq[Q];
+
+    __device__ __forceinline__ Down2Walk(const ResizeArgs &a_, const unsigned char *s,
+                                         unsigned char *d, int32_t c0, int32_t yb, int32_t ye)
+        : a(a_), src(s), dst(d), col0(c0), run0(WIDE ? 2 * c0 - PAD : 2 * c0 + LO), y_b(yb), y_e(ye)
+    {
+        weights<FILTER>(0.5f, 0.5f, w);
+    }
+
+    // Rows are clamped into the stored band (which holds every row a needed
+    // tap reads) and to r_last (requests past it re-read that row).
+    __device__ __forceinline__ Raw load_row(int32_t r) const
+    {
+        const int32_t rr = clampi(min(r, r_last), a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
+        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
+        if constexpr (WIDE) {
+            return load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
+        } else {
+            Raw raw;
+#pragma unroll
+            for (int s = 0; s < SPAN; ++s)
+                copy_pixel<PB>(raw.b + s * PB,
+                               row + static_cast<int64_t>(clampi(run0 + s, 0, a.in_w - 1)) * PB);
+            return raw;
+        }
+    }
+
+    __device__ __forceinline__ void hfilter(const Raw &raw, float (&out)[PPX][C]) const
+    {
+        float p[NEED][C];
+#pragma unroll
+        for (int s = 0; s < NEED; ++s)
+            decode<T, C>(raw.b, OFF + s, p[s]);
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            fma_first(out[c], w[0], p[2 * c]);
+#pragma unroll
+            for (int i = 1; i < K; ++i)
+                fma_next(out[c], w[i], p[2 * c + i]);
+        }
+    }
+
+    // output row y from the window whose oldest row sits in ring slot OLD
+    template <int OLD>
+    __device__ __forceinline__ void emit(int32_t y)
+    {
+        unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
+        float v[PPX][C];
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            fma_first(v[c], w[0], ring[OLD % K][c]);
+#pragma unroll
+            for (int j = 1; j < K; ++j)
+                fma_next(v[c], w[j], ring[(OLD + j) % K][c]);
+        }
+        if constexpr (WIDE) {
+            RawBuf<PPX * PB, OUT_ALIGN> out;
+            encode_run<T, C, PPX>(v, out);
+            store_raw<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
+        } else {
+            const int32_t ncols = min(PPX, a.out_w - col0);
+#pragma unroll
+            for (int c = 0; c < PPX; ++c)
+                if (c < ncols)
+                    Pix<T, C>::store(drow, col0 + c, v[c]);
+        }
+    }
+
+    // filter source row r_first + I (requesting row r_first + I + PD first)
+    template <int I>
+    __device__ __forceinline__ void filter(int32_t r)
+    {
+        rawq[(I + PD) % Q] = load_row(r + PD);
+        hfilter(rawq[I % Q], ring[I % K]);
+    }
+
+    __device__ __forceinline__ void run()
+    {
+        // output y reads source rows 2y + LO .. 2y + LO + K - 1; row
+        // r_first + i sits in ring slot i mod K
+        const int32_t r_first = 2 * y_b + LO;
+        r_last = 2 * (y_e - 1) + LO + K - 1;
+#pragma unroll
+        for (int i = 0; i < PD; ++i)
+            rawq[i % Q] = load_row(r_first + i);
+        // rows r_first .. r_first + K - 3 come before the first output row's
+        // last two rows
+        if constexpr (K == 4) {
+            filter<0>(r_first);
+            filter<1>(r_first + 1);
+        }
+        // output y = y_b + 2m + e completes with source rows
+        // r_first + 4m + 2e + K - 2 and + K - 1
+        constexpr int B = K - 2;  // index of the first row filtered in the loop
+        for (int32_t y = y_b; y < y_e; y += 2) {
+            const int32_t r = r_first + 2 * (y - y_b) + B;
+            filter<B>(r);
+            filter<B + 1>(r + 1);
+            emit<B + 2 - K>(y);
+            filter<B + 2>(r + 2);
+            filter<B + 3>(r + 3);
+            if (y + 1 < y_e)
+                emit<B + 4 - K>(y + 1);
+        }
+    }
+};
+
+template <int FILTER, typename T, int C, int PPX>
+__global__ void __launch_bounds__(512) k_strip_down2(ResizeArgs a, int32_t strip_h, int32_t order)
+{
+    using W = Down2Walk<FILTER, T, C, PPX, true>;
+    int32_t bx, by;
+    tile_coords(order, bx, by);
+    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + threadIdx.x) * PPX;
+    const int32_t r_begin = strip_begin(by, strip_h);
+    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+        return;
+    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
+    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
+    const int32_t run0 = 2 * col0 - W::PAD;
+    const bool wide = a.aligned16 && run0 >= 0 && run0 + W::SPAN <= a.in_w && col0 + PPX <= a.out_w;
+    if (wide) {
+        W w(a, src, dst, col0, y_b, y_e);
+        w.run();
+    } else {
+        Down2Walk<FILTER, T, C, PPX, false> w(a, src, dst, col0, y_b, y_e);
+        w.run();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // k_batched: one persistent launch over every tile of every job
 // ---------------------------------------------------------------------------
 //
@@ -917,14 +1090,17 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
     const dim3 block(tile.block_w, tile.block_h, 1);
     const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
                     (a.dst_rows + rows_per_block - 1) / rows_per_block, a.planes);
-#define XR_STRIP_CASE(P)                                                                   \
-    case P:                                                                                \
-        if (mode == kUp2)                                                                  \
-            hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,  \
-                               tile.ppt_y, tile.order);                                    \
-        else                                                                               \
-            hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a,      \
-                               tile.ppt_y, tile.order);                                    \
+#define XR_STRIP_CASE(P)                                                                    \
+    case P:                                                                                 \
+        if (mode == kUp2)                                                                   \
+            hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,   \
+                               tile.ppt_y, tile.order);                                     \
+        else if (mode == kDown2)                                                            \
+            hipLaunchKernelGGL((k_strip_down2<FILTER, T, C, P>), grid, block, 0, stream, a, \
+                               tile.ppt_y, tile.order);                                     \
+        else                                                                                \
+            hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a,       \
+                               tile.ppt_y, tile.order);                                     \
         return hipGetLastError();
     if constexpr (C == 4) {
         switch (tile.ppt_x) {

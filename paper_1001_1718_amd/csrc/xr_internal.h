@@ -53,7 +53,7 @@ struct BatchHeader {
 constexpr size_t kBatchHeaderBytes = 256;
 
 // Shape of an axis that a kernel can specialise on.
-enum AxisMode : int32_t { kGeneral = 0, kUp2 = 1 };
+enum AxisMode : int32_t { kGeneral = 0, kUp2 = 1, kDown2 = 2 };
 
 hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
                           const xr_tile &tile, int32_t mode, hipStream_t stream);

@@ -45,6 +45,22 @@ def _tile_for(name, channels):
     return t
 
 
+def _lds_stageable(t, in_w, out_w, mode, dtype, channels):
+    """The staging rule of XR_KERNEL_STRIP_LDS: a workgroup's source segment
+    of at most floor((cols - 1) * in_w / out_w) + K + 1 pixels, moved in
+    chunks of max(pixel, 4) bytes, must need at most 64 / chunk chunks per
+    lane and three row buffers of at most 64 KiB; pixels under 4 bytes need
+    rows of whole 4-byte words."""
+    pb = channels * np.dtype(dtype).itemsize
+    cb = max(pb, 4)
+    k = 4 if mode == "bicubic" else 2
+    cols = min(t.block_w * t.ppt_x, out_w)
+    seg = (cols - 1) * in_w // out_w + k + 1
+    chunks = -(-(seg * pb + cb - pb) // cb)
+    need = -(-chunks // t.block_w)
+    return need <= 64 // cb and 3 * (-(-chunks * cb // 16) * 16) <= 65536 and (pb >= 4 or (in_w * pb) % 4 == 0)
+
+
 def _input(dtype, h, w, c, seed):
     if dtype == np.uint8:
         return fields.uniform_u8((h, w, c), seed)
@@ -71,6 +87,8 @@ SHAPES = [
     ((40, 32), (80, 64)),    # exact x2, aligned
     ((37, 53), (61, 29)),    # non-dyadic up / down
     ((64, 96), (32, 48)),    # exact x0.5
+    ((74, 262), (37, 131)),  # exact x0.5, ragged, several strips
+    ((2, 2), (1, 1)),        # exact x0.5, every tap clamped
     ((33, 21), (33, 21)),    # identity
     ((1, 5), (3, 7)),        # one-row source
     ((9, 1), (20, 2)),       # one-column source
@@ -88,9 +106,8 @@ def test_small_all_kernels(shape, dtype, channels, mode):
     outs = {}
     for name in TILES:
         t = _tile_for(name, channels)
-        if name.startswith("strip_lds") and (in_w * channels * np.dtype(dtype).itemsize) % 4:
-            # the LDS walk stages small pixels as 4-byte words: rows that are
-            # not whole words are refused, not read past their end
+        if name.startswith("strip_lds") and not _lds_stageable(t, in_w, out_w, mode, dtype, channels):
+            # refused (XR_ERR_ARG), never read past a row or the LDS budget
             with pytest.raises(xr.XResizeError) as e:
                 _gpu(img, out_h, out_w, mode, t)
             assert e.value.code == 11
@@ -141,17 +158,23 @@ def test_lds_strip_rejects_what_it_cannot_stage():
 
 
 @pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
-def test_bands_match_whole_image(mode):
+@pytest.mark.parametrize("out_hw", [(194, 160), (48, 40)], ids=["x2", "x0.5"])
+def test_bands_match_whole_image(mode, out_hw):
     img = fields.field_unit(97, 80, 1, seed=5, dtype=np.float16)[:, :, 0]
-    out_h, out_w = 194, 160
+    if out_hw[0] < 97:
+        img = img[:96]
+    out_h, out_w = out_hw
     whole = _gpu(img, out_h, out_w, mode)
     x = torch.from_numpy(img).to(DEV)
+    in_h = img.shape[0]
     bands = []
-    for row0, rows in [(0, 61), (61, 1), (62, 70), (132, 62)]:
-        first, last = xr.needed_rows(97, out_h, row0, rows, mode)
+    cuts = [0, 61, 62, 132, 194] if out_h == 194 else [0, 13, 14, 31, 48]
+    for row0, row1 in zip(cuts[:-1], cuts[1:]):
+        rows = row1 - row0
+        first, last = xr.needed_rows(in_h, out_h, row0, rows, mode)
         src_band = x[first:last + 1].contiguous()
         dst_band = torch.empty((rows, out_w), dtype=x.dtype, device=DEV)
-        xr.resize_into(src_band, dst_band, mode, src_row0=first, src_height=97, dst_row0=row0,
+        xr.resize_into(src_band, dst_band, mode, src_row0=first, src_height=in_h, dst_row0=row0,
                        dst_height=out_h)
         bands.append(dst_band)
     torch.cuda.synchronize()
