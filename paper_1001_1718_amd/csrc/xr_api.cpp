@@ -237,32 +237,55 @@ TuneKey tune_key(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, 
 std::mutex g_tune_mu;
 std::map<TuneKey, xr_tile> g_tuned;
 
-// Untuned launch shape: 256-wide workgroups (four wavefronts on the same
-// rows), 4 (RGBA) or 8 (one channel) columns per thread, and the longest
-// strip of the form 8m - 2 rows that still gives about 8 wavefronts per SIMD
-// (2048 x 4); small outputs fall back to narrower runs and single rows.
-xr_tile default_tile(int32_t channels, int32_t out_w, int32_t rows, int32_t planes)
+// Untuned launch shape, by scale (the tuner's typical winners on MI355X):
+//  exact x2     256x1 threads, 4 (RGBA) or 8 (one channel) columns per
+//               thread, strips of 14 rows;
+//  exact x0.5   512x1 threads, 2 or 4 columns, strips of 6 rows;
+//  other        128x2 threads, 2 or 4 columns, strips of 30 rows when the
+//               rows grow, 6 when they shrink (a strip then walks several
+//               source rows per output row).
+// Strips are shortened (14/30 -> 6 -> 2 -> 1 rows) until the launch has about
+// 8 wavefronts per SIMD (2048 x 4); tiny outputs use 64-wide workgroups.
+xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w, int32_t rows,
+                     int32_t out_h, int32_t planes)
 {
+    const bool c4 = channels == 4;
     xr_tile t{};
     t.kernel = XR_KERNEL_STRIP;
-    t.block_w = 256;
-    t.block_h = 1;
-    t.ppt_x = channels == 4 ? 4 : 8;
-    t.ppt_y = 14;
     t.order = 0;
+    int first;
+    if (out_w == 2 * in_w && out_h == 2 * in_h) {
+        t.block_w = 256;
+        t.block_h = 1;
+        t.ppt_x = c4 ? 4 : 8;
+        first = 14;
+    } else if (2 * out_w == in_w && 2 * out_h == in_h) {
+        t.block_w = 512;
+        t.block_h = 1;
+        t.ppt_x = c4 ? 2 : 4;
+        first = 6;
+    } else {
+        t.block_w = 128;
+        t.block_h = 2;
+        t.ppt_x = c4 ? 2 : 4;
+        first = out_h >= in_h ? 30 : 6;
+    }
     const auto waves = [&](const xr_tile &u) {
         const int64_t wcols = (static_cast<int64_t>(out_w) + 64 * u.ppt_x - 1) / (64 * u.ppt_x);
         return wcols * ((static_cast<int64_t>(rows) + u.ppt_y - 1) / u.ppt_y) * planes;
     };
     const int64_t target = 8192;
-    const int steps[] = {14, 6, 2, 1};
+    const int steps[] = {first, 6, 2, 1};
     for (int ppy : steps) {
+        if (ppy > first)
+            continue;
         t.ppt_y = ppy;
         if (waves(t) >= target)
             return t;
     }
-    t.ppt_x = channels == 4 ? 2 : 4;
+    t.ppt_x = c4 ? 2 : 4;
     t.block_w = 64;
+    t.block_h = 1;
     return t;
 }
 
@@ -344,7 +367,8 @@ xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, c
     if (it != g_tuned.end() &&
         (it->second.kernel != XR_KERNEL_STRIP_LDS || lds_usable(it->second, filter, src, dst)))
         return it->second;
-    return default_tile(src.channels, dst.width, dst.rows, dst.planes);
+    return default_tile(src.channels, src.width, src.height, dst.width, dst.rows, dst.height,
+                        dst.planes);
 }
 
 int check_grid(const xr_tile &t, const xr_image &dst)
@@ -487,7 +511,6 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     auto *hdr = reinterpret_cast<xr::BatchHeader *>(host.data());
     auto *tab = reinterpret_cast<xr::BatchJob *>(host.data() + xr::kBatchHeaderBytes);
     const int64_t tile_w = static_cast<int64_t>(t.block_w) * xr::kBatchPpx;
-    const int64_t tile_h = static_cast<int64_t>(t.block_h) * t.ppt_y;
     int64_t total = 0;
     for (int32_t k = 0; k < n_jobs; ++k) {
         const xr_job &j = jobs[order[k]];
@@ -495,6 +518,12 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
         b.a = make_args(j.src, j.dst);
         b.filter = j.filter;
         b.channels = j.src.channels;
+        // a strip walks about ppt_y source rows or ppt_y output rows, whichever
+        // is fewer output rows, so shrinking jobs do not make long tiles
+        b.strip_h = static_cast<int32_t>(std::max<int64_t>(
+            1, std::min<int64_t>(t.ppt_y, (static_cast<int64_t>(t.ppt_y) * j.dst.height +
+                                           j.src.height - 1) / j.src.height)));
+        const int64_t tile_h = static_cast<int64_t>(t.block_h) * b.strip_h;
         b.tiles_x = static_cast<int32_t>((j.dst.width + tile_w - 1) / tile_w);
         b.tiles_y = static_cast<int32_t>((j.dst.rows + tile_h - 1) / tile_h);
         b.tile_begin = total;
@@ -867,7 +896,8 @@ int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
         return fail(XR_ERR_SHAPE, "sizes must be positive");
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h));
-    *out = it != g_tuned.end() ? it->second : default_tile(channels, out_w, out_h, 1);
+    *out = it != g_tuned.end() ? it->second
+                               : default_tile(channels, in_w, in_h, out_w, out_h, out_h, 1);
     return XR_OK;
 }
 

@@ -877,7 +877,7 @@ __global__ void __launch_bounds__(512) k_strip_down2(ResizeArgs a, int32_t strip
 // Workgroups take tiles from a global ticket counter (jobs are ordered largest
 // first, so the long tiles start early and short ones fill the tail). A tile
 // is a (blockDim.x * kBatchPpx) x (blockDim.y * strip_h) block of one plane
-// of one job; filter and channel count are uniform per tile, so the branch
+// of one job (strip_h per job: shorter for jobs whose rows shrink); filter and channel count are uniform per tile, so the branch
 // to the right strip body is uniform. The last workgroup to finish resets the
 // counters, so the launch can be replayed (e.g. from a HIP graph) without any
 // host-side clearing.
@@ -897,7 +897,6 @@ __global__ void __launch_bounds__(256) k_batched(unsigned char *ws)
     const BatchJob *jobs = reinterpret_cast<const BatchJob *>(ws + kBatchHeaderBytes);
     const int64_t total = hdr->total_tiles;
     const int32_t n_jobs = hdr->n_jobs;
-    const int32_t strip_h = hdr->ppt_y;
     __shared__ uint32_t s_tile;
     const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
     for (;;) {
@@ -925,6 +924,7 @@ __global__ void __launch_bounds__(256) k_batched(unsigned char *ws)
         const int32_t ty = rem / job.tiles_x;
         const int32_t tx = rem - ty * job.tiles_x;
         const int32_t col0 = (tx * blockDim.x + threadIdx.x) * kBatchPpx;
+        const int32_t strip_h = job.strip_h;
         const int32_t r_begin =
             __builtin_amdgcn_readfirstlane((ty * blockDim.y + threadIdx.y) * strip_h);
         if (col0 < a.out_w && r_begin < a.dst_rows) {

@@ -36,6 +36,8 @@ struct BatchJob {
     int32_t tiles_x;         // tiles per row of the output (per plane)
     int32_t tiles_y;         // tiles per column of the output (per plane)
     int64_t tile_begin;      // prefix sum of tiles of the jobs before this one
+    int32_t strip_h;         // output rows per thread strip of this job
+    int32_t pad_;
 };
 
 // Header of the batched workspace; jobs follow at offset kBatchHeaderBytes.
@@ -45,7 +47,7 @@ struct BatchHeader {
     int32_t dtype;
     int32_t block_w;         // threads per workgroup along x
     int32_t block_h;         // thread rows per workgroup
-    int32_t ppt_y;           // rows per thread strip
+    int32_t ppt_y;           // rows per thread strip (before per-job scaling)
     int32_t grid;            // workgroups of the persistent launch
     uint32_t ticket;         // next tile to hand out (self-resetting)
     uint32_t done;           // workgroups that have finished (self-resetting)
