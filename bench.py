@@ -26,6 +26,7 @@ Printed JSON line (one):
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--no-batch] [--no-tune] [--extras]
+       python bench.py --paper-sweep   (the paper's tile experiment only)
 """
 
 from __future__ import annotations
@@ -402,6 +403,51 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
     return out
 
 
+PAPER_SHAPES = [(8, 8), (32, 4), (32, 16), (4, 8), (8, 4)]
+
+
+def paper_sweep(torch, xr, fields, reps: int = 10, groups: int = 3):
+    """The paper's tile-shape experiment on this GPU: bilinear resize of an
+    800 x 800 image (smooth-field stand-in, RGBA uint8) by 2, 4, 6, 8 and 10,
+    every output pixel one thread in a block_w x block_h block (the paper's
+    own tiling, eq. 6) for the paper's shapes and a few wider ones, next to
+    the strip walks. Median of `groups` groups of `reps` launches per shape,
+    rotating over enough buffers to exceed the Infinity Cache."""
+    dev = torch.device("cuda:0")
+    src0 = fields.field_u8_torch(800, 800, 4, 1001, dev)
+    gather = PAPER_SHAPES + [(16, 16), (64, 4), (64, 1), (128, 2), (256, 1)]
+    out = {}
+    for scale in (2, 4, 6, 8, 10):
+        n = 800 * scale
+        n_buf = max(1, math.ceil(ROTATE_BYTES / (n * n * 4)))
+        srcs = [src0.clone() for _ in range(n_buf)]
+        dsts = [torch.empty((n, n, 4), dtype=torch.uint8, device=dev) for _ in range(n_buf)]
+        times = {}
+        for bw, bh in gather:
+            _, ms = xr.autotune(srcs, dsts, "bilinear", candidates=[xr.tile(xr.XR_KERNEL_GATHER, bw, bh)],
+                                reps=reps, groups=groups)
+            times[f"gather {bw}x{bh}"] = ms
+        strip = [c for c in xr.tune_candidates("bilinear", xr.XR_U8, 4, 800, 800, n, n)
+                 if c.kernel in (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS)]
+        best_strip, ms = xr.autotune(srcs, dsts, "bilinear", candidates=strip, reps=reps, groups=groups)
+        paper = {k: v for k, v in times.items() if tuple(int(x) for x in k.split()[1].split("x")) in PAPER_SHAPES}
+        best_paper = min(paper, key=paper.get)
+        worst_paper = max(paper, key=paper.get)
+        out[f"x{scale}"] = {
+            "output": f"{n}x{n}",
+            "gather_us": {k: round(v * 1e3, 1) for k, v in times.items()},
+            "best_paper_shape": best_paper,
+            "paper_spread_worst_over_best": round(paper[worst_paper] / paper[best_paper], 3),
+            "best_strip": repr(best_strip),
+            "best_strip_us": round(ms * 1e3, 1),
+            "strip_speedup_over_best_paper_shape": round(paper[best_paper] / ms, 2),
+        }
+        log(f"paper sweep x{scale}: {out[f'x{scale}']}")
+        del srcs, dsts
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -415,6 +461,9 @@ def main():
                     help="fixed launch shape KIND,BW,BH,PPX,PPY[,ORDER] (kind 1 gather, 2 strip) instead of tuning")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for hardware counters)")
+    ap.add_argument("--paper-sweep", action="store_true",
+                    help="only run the paper's tile-shape experiment (800x800 bilinear x2..x10) and "
+                         "print its JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -431,6 +480,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.paper_sweep:
+        print(json.dumps({"paper_tile_sweep": paper_sweep(torch, xr, fields), "dtype": "u8",
+                          "data": "synthetic"}), flush=True)
+        return
     if args.calibrate:
         a = torch.ones(256 << 20, dtype=torch.uint8, device="cuda:0")
         b = torch.empty_like(a)
