@@ -12,6 +12,8 @@ coordinate of output index x is taken at pixel centres,
 
     s(x) = ((2x + 1) N_in - N_out) / (2 N_out)        (eq. 1, half-pixel reading)
 
+or, with mapping=CORNER, as eq. 1 prints it, s(x) = x N_in / N_out.
+
 the base tap is x0 = floor(s) and the fractional offset t = s - x0
 (eqs. 2-4, with int() read as floor). Bilinear uses taps x0, x0+1 with weights
 (1 - t, t); Keys bicubic uses taps x0-1 .. x0+2 with weights K(t - j) for
@@ -22,7 +24,9 @@ to [0, N_in - 1] (replicate edge). An output value is
 
 (eq. 5, with the second bracket's weight read as (1 - offsetX) so that the four
 weights sum to one). Everything is evaluated in float64. The adjoint scatters
-wy_j wx_i g[y][x] onto the same clamped taps.
+wy_j wx_i g[y][x] onto the same clamped taps. Nearest neighbour (named among
+the paper's interpolation methods in section II) takes the one source pixel
+whose area contains the mapped point.
 
 Images are arrays of shape (planes, height, width, channels).
 
@@ -37,18 +41,45 @@ import numpy as np
 
 BILINEAR = 0
 BICUBIC = 1
+NEAREST = 2
 KEYS_A = -0.5
 
+HALF_PIXEL = 0  # pixel centres aligned: s = (x + 1/2) n_in / n_out - 1/2
+CORNER = 1      # eq. 1 as printed: s = x_f / scale with scale = n_out / n_in
 
-def source_coordinate(x, n_in: int, n_out: int):
-    """Half-pixel form of eq. 1: s = ((2x+1) n_in - n_out) / (2 n_out), in float64.
 
+def source_coordinate(x, n_in: int, n_out: int, mapping: int = HALF_PIXEL):
+    """Source coordinate of output index x (eq. 1), in float64.
+
+    HALF_PIXEL: s = ((2x+1) n_in - n_out) / (2 n_out) (pixel centres aligned);
+    CORNER:     s = x n_in / n_out (eq. 1 as printed, x_p = x_f / scale, the
+                scale taken from the two sizes).
     The numerator and denominator are exact integers, so s carries a single
     rounding.
     """
     x = np.asarray(x, dtype=np.int64)
-    num = (2 * x + 1) * int(n_in) - int(n_out)
-    return num.astype(np.float64) / float(2 * int(n_out))
+    if mapping == HALF_PIXEL:
+        num, den = (2 * x + 1) * int(n_in) - int(n_out), 2 * int(n_out)
+    elif mapping == CORNER:
+        num, den = x * int(n_in), int(n_out)
+    else:
+        raise ValueError(f"unknown mapping {mapping}")
+    return num.astype(np.float64) / float(den)
+
+
+def nearest_index(x, n_in: int, n_out: int, mapping: int = HALF_PIXEL):
+    """Nearest neighbour: the source pixel whose area contains the mapped
+    point. Pixel i covers [i - 1/2, i + 1/2) in half-pixel coordinates and
+    [i, i + 1) in the corner convention, so the index is floor(s + 1/2),
+    respectively floor(s), from exact integers; clamped to [0, n_in - 1]."""
+    x = np.asarray(x, dtype=np.int64)
+    if mapping == HALF_PIXEL:
+        idx = ((2 * x + 1) * int(n_in)) // (2 * int(n_out))  # floor(s + 1/2)
+    elif mapping == CORNER:
+        idx = (x * int(n_in)) // int(n_out)                    # floor(s)
+    else:
+        raise ValueError(f"unknown mapping {mapping}")
+    return np.clip(idx, 0, int(n_in) - 1)
 
 
 def keys_kernel(d, a: float = KEYS_A):
@@ -64,14 +95,17 @@ def keys_kernel(d, a: float = KEYS_A):
     return np.where(d <= 1.0, near, np.where(d < 2.0, far, 0.0))
 
 
-def axis_taps(n_in: int, n_out: int, filt: int, a: float = KEYS_A):
+def axis_taps(n_in: int, n_out: int, filt: int, a: float = KEYS_A, mapping: int = HALF_PIXEL):
     """Per output index: clamped tap indices and float64 weights.
 
-    Returns (idx, w, x0, t) with idx, w of shape (n_out, k), k = 2 (bilinear)
-    or 4 (bicubic); idx[x, j] is the clamped source index of tap j and w[x, j]
-    its weight; x0 = floor(s) and t = s - x0 (eqs. 2-4).
+    Returns (idx, w, x0, t) with idx, w of shape (n_out, k), k = 1 (nearest),
+    2 (bilinear) or 4 (bicubic); idx[x, j] is the clamped source index of tap
+    j and w[x, j] its weight; x0 = floor(s) and t = s - x0 (eqs. 2-4).
     """
-    s = source_coordinate(np.arange(n_out), n_in, n_out)
+    if filt == NEAREST:
+        idx = nearest_index(np.arange(n_out), n_in, n_out, mapping)
+        return idx[:, None], np.ones((n_out, 1)), idx, np.zeros(n_out)
+    s = source_coordinate(np.arange(n_out), n_in, n_out, mapping)
     x0 = np.floor(s)
     t = s - x0
     x0 = x0.astype(np.int64)
@@ -99,7 +133,7 @@ def _as_planes(img) -> np.ndarray:
 
 
 def resize_rows(img, out_h: int, out_w: int, rows, filt: int, a: float = KEYS_A,
-                absolute: bool = False) -> np.ndarray:
+                absolute: bool = False, mapping: int = HALF_PIXEL) -> np.ndarray:
     """Output rows ``rows`` of the resize of ``img`` (P, H, W, C) to (out_h, out_w).
 
     Returns float64 of shape (P, len(rows), out_w, C). Direct double sum over
@@ -112,8 +146,8 @@ def resize_rows(img, out_h: int, out_w: int, rows, filt: int, a: float = KEYS_A,
         src = np.abs(src)
     _, in_h, in_w, _ = src.shape
     rows = np.asarray(rows, dtype=np.int64)
-    iy, wy, _, _ = axis_taps(in_h, out_h, filt, a)
-    ix, wx, _, _ = axis_taps(in_w, out_w, filt, a)
+    iy, wy, _, _ = axis_taps(in_h, out_h, filt, a, mapping)
+    ix, wx, _, _ = axis_taps(in_w, out_w, filt, a, mapping)
     iy, wy = iy[rows], wy[rows]
     if absolute:
         wy, wx = np.abs(wy), np.abs(wx)
@@ -127,9 +161,10 @@ def resize_rows(img, out_h: int, out_w: int, rows, filt: int, a: float = KEYS_A,
     return out
 
 
-def resize(img, out_h: int, out_w: int, filt: int, a: float = KEYS_A) -> np.ndarray:
+def resize(img, out_h: int, out_w: int, filt: int, a: float = KEYS_A,
+           mapping: int = HALF_PIXEL) -> np.ndarray:
     """Whole-image resize, float64, shape (P, out_h, out_w, C)."""
-    return resize_rows(img, out_h, out_w, np.arange(out_h), filt, a)
+    return resize_rows(img, out_h, out_w, np.arange(out_h), filt, a, mapping=mapping)
 
 
 def adjoint(grad_out, in_h: int, in_w: int, filt: int, a: float = KEYS_A,
@@ -159,9 +194,10 @@ def adjoint(grad_out, in_h: int, in_w: int, filt: int, a: float = KEYS_A,
     return gs
 
 
-def axis_matrix(n_in: int, n_out: int, filt: int, a: float = KEYS_A) -> np.ndarray:
+def axis_matrix(n_in: int, n_out: int, filt: int, a: float = KEYS_A,
+                mapping: int = HALF_PIXEL) -> np.ndarray:
     """Dense (n_out, n_in) interpolation matrix of one axis: A[x, idx] += w."""
-    idx, w, _, _ = axis_taps(n_in, n_out, filt, a)
+    idx, w, _, _ = axis_taps(n_in, n_out, filt, a, mapping)
     m = np.zeros((n_out, n_in), dtype=np.float64)
     for j in range(idx.shape[1]):
         np.add.at(m, (np.arange(n_out), idx[:, j]), w[:, j])
@@ -178,9 +214,10 @@ def quantize_f16(v) -> np.ndarray:
     return np.asarray(v, dtype=np.float64).astype(np.float16)
 
 
-def needed_rows(in_h: int, out_h: int, row0: int, rows: int, filt: int):
+def needed_rows(in_h: int, out_h: int, row0: int, rows: int, filt: int,
+                mapping: int = HALF_PIXEL):
     """Inclusive range of clamped source rows that output rows [row0, row0+rows) read."""
-    iy, _, _, _ = axis_taps(in_h, out_h, filt)
+    iy, _, _, _ = axis_taps(in_h, out_h, filt, mapping=mapping)
     sel = iy[row0:row0 + rows]
     return int(sel.min()), int(sel.max())
 

@@ -6,6 +6,8 @@
 * replays from a captured HIP graph, with eager work in between, equal the
   eager result every time (the ticket counter resets itself);
 * the full 256-job batch: bitwise equal to 256 per-image launches;
+* FP16 interleaved and FP32 planar (NCHW, several planes per job) batches;
+* the batch autotuner keeps results bitwise unchanged;
 * host-side validation of prepare (capture, workspace, dtype mix).
 """
 
@@ -112,6 +114,43 @@ def test_full_batch_bitwise_equal_to_per_image():
         rows = rng.integers(0, j.out_h, 1)
         got = d[torch.from_numpy(rows).to(DEV)].cpu().numpy()
         compare(got[None], s.cpu().numpy(), j.out_h, j.out_w, f, rows=rows, what=f"job {k}")
+
+
+@pytest.mark.parametrize("dtype", [torch.float16, torch.float32], ids=["f16", "f32"])
+def test_float_batches(dtype):
+    """FP16 interleaved (1 and 4 channels) and FP32 planar NCHW jobs."""
+    jobs = fields.batch_jobs(21, count=12, side_hi=260)
+    pairs, layout = [], "hwc" if dtype == torch.float16 else "nchw"
+    for j in jobs:
+        if layout == "hwc":
+            s = torch.from_numpy(fields.field_unit(j.in_h, j.in_w, j.channels, j.content_seed,
+                                                   np.float16)).to(DEV)
+            d = torch.empty((j.out_h, j.out_w, j.channels), dtype=dtype, device=DEV)
+        else:  # N = 2 images of C = channels planes
+            s = torch.from_numpy(fields.normal_f32((2, j.channels, j.in_h, j.in_w), j.content_seed)).to(DEV)
+            d = torch.empty((2, j.channels, j.out_h, j.out_w), dtype=dtype, device=DEV)
+        pairs.append((s, d, j.filter))
+    ref = []
+    for s, d, f in pairs:
+        o = torch.empty_like(d)
+        xr.resize_into(s, o, f, layout=layout)
+        ref.append(o)
+    b = xr.Batch(pairs, layout=layout)
+    b.run()
+    torch.cuda.synchronize()
+    for k, ((s, d, f), r) in enumerate(zip(pairs, ref)):
+        assert torch.equal(d, r), f"job {k}: batched output differs from the per-image launch"
+    rng = np.random.default_rng(5)
+    for k, (j, (s, d, f)) in enumerate(zip(jobs, pairs)):
+        rows = np.unique(np.concatenate([[0, j.out_h - 1], rng.integers(0, j.out_h, 2)]))
+        src = s.cpu().numpy()
+        if layout == "hwc":
+            got = d[torch.from_numpy(rows).to(DEV)].cpu().numpy()[None]
+            compare(got, src, j.out_h, j.out_w, f, rows=rows, what=f"f16 job {k}")
+        else:
+            planes = src.reshape(-1, j.in_h, j.in_w)[:, :, :, None]
+            got = d.reshape(-1, j.out_h, j.out_w)[:, torch.from_numpy(rows).to(DEV)].cpu().numpy()[..., None]
+            compare(got, planes, j.out_h, j.out_w, f, rows=rows, what=f"f32 job {k}")
 
 
 def test_batch_autotune_picks_a_candidate_and_keeps_results():

@@ -6,7 +6,10 @@
   (tests/golden/), plus invariants (partition of unity, moment reproduction);
 * special cases: identity size, constants, ramps, quadratics;
 * independent library routines: torch interpolate (bilinear; bicubic with
-  a = -3/4) and its backward, PIL float-mode bicubic in the interior;
+  a = -3/4; nearest-exact and nearest for the nearest filter under the two
+  maps) and its backward, PIL float-mode bicubic in the interior;
+* the paper's printed map (eq. 1, x_p = x_f / scale): exact brute force, the
+  x2 closed form, and eqs. 1-5 evaluated literally pixel by pixel;
 * adjoint by finite differences, by <Ax, y> = <x, A^T y> and by mass conservation;
 * a mutation check: plausible mistakes planted into a copy of the oracle must
   be caught by the brute-force pin.
@@ -40,12 +43,16 @@ def _kernel_exact(d: Fraction, filt: int, a: Fraction) -> Fraction:
     return Fraction(0)
 
 
-def _axis_exact(n_in: int, n_out: int, filt: int, a: Fraction):
+def _axis_exact(n_in: int, n_out: int, filt: int, a: Fraction, corner: bool = False):
     """Dense exact (n_out, n_in) matrix from the all-i form: every integer i in a
-    generous window contributes K(s - i) to column clamp(i)."""
+    generous window contributes K(s - i) to column clamp(i). s is the pixel
+    centre map, or with `corner` the paper's printed map x * n_in / n_out."""
     m = [[Fraction(0)] * n_in for _ in range(n_out)]
     for x in range(n_out):
-        s = Fraction((2 * x + 1) * n_in - n_out, 2 * n_out)
+        if corner:
+            s = Fraction(x * n_in, n_out)
+        else:
+            s = Fraction((2 * x + 1) * n_in - n_out, 2 * n_out)
         lo = int(s) - 6
         for i in range(lo, lo + 13):
             w = _kernel_exact(s - i, filt, a)
@@ -54,10 +61,10 @@ def _axis_exact(n_in: int, n_out: int, filt: int, a: Fraction):
     return m
 
 
-def _brute_resize(img2d, out_h, out_w, filt, a=Fraction(-1, 2)):
+def _brute_resize(img2d, out_h, out_w, filt, a=Fraction(-1, 2), corner=False):
     in_h, in_w = len(img2d), len(img2d[0])
-    ay = _axis_exact(in_h, out_h, filt, a)
-    ax = _axis_exact(in_w, out_w, filt, a)
+    ay = _axis_exact(in_h, out_h, filt, a, corner)
+    ax = _axis_exact(in_w, out_w, filt, a, corner)
     out = []
     for y in range(out_h):
         row = []
@@ -113,6 +120,17 @@ def test_brute_force_exact(shape, filt):
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
     got_c = ref_c.resize(img, out_h, out_w, filt)[0, :, :, 0]
     np.testing.assert_allclose(got_c, want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_brute_force_exact_corner_mapping(shape, filt):
+    in_h, in_w, out_h, out_w = shape
+    img = fields.uniform_u8((in_h, in_w), seed=13 + in_h * 31 + in_w)
+    exact = _brute_resize(img.tolist(), out_h, out_w, filt, corner=True)
+    got = R.resize(img, out_h, out_w, filt, mapping=R.CORNER)[0, :, :, 0]
+    want = np.array([[float(v) for v in row] for row in exact])
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
 
 
 @pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
@@ -306,6 +324,65 @@ def test_torch_bilinear_backward_pin(sizes):
                                rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("sizes", [(16, 16, 32, 32), (13, 17, 29, 23), (40, 31, 17, 12), (9, 9, 9, 9),
+                                   (7, 30, 50, 4), (1, 5, 3, 11)])
+def test_torch_nearest_pins(sizes):
+    """Nearest neighbour: pixel-centre map == torch 'nearest-exact', the
+    paper's printed map == torch 'nearest' (both FP64, exact copies)."""
+    in_h, in_w, out_h, out_w = sizes
+    img = fields.normal_f32((in_h, in_w), seed=23).astype(np.float64)
+    t = torch.from_numpy(img)[None, None]
+    exact = F.interpolate(t, size=(out_h, out_w), mode="nearest-exact")[0, 0].numpy()
+    legacy = F.interpolate(t, size=(out_h, out_w), mode="nearest")[0, 0].numpy()
+    np.testing.assert_array_equal(R.resize(img, out_h, out_w, R.NEAREST)[0, :, :, 0], exact)
+    np.testing.assert_array_equal(
+        R.resize(img, out_h, out_w, R.NEAREST, mapping=R.CORNER)[0, :, :, 0], legacy)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 16])
+def test_corner_mapping_x2_closed_form(n):
+    """Eq. 1 as printed at x2: s = x / 2, so even outputs copy source pixel
+    x / 2 (t = 0) and odd outputs sit halfway (t = 1/2): bilinear averages
+    the two neighbours, Keys a = -1/2 weighs four by (-1, 9, 9, -1) / 16,
+    taps clamped to the image."""
+    row = fields.uniform_u8((1, n), seed=n).astype(np.float64)[0]
+    img = np.tile(row, (3, 1))  # constant columns: only the x axis matters
+
+    def px(i):
+        return row[min(max(i, 0), n - 1)]
+
+    bil = R.resize(img, 3, 2 * n, R.BILINEAR, mapping=R.CORNER)[0, 1, :, 0]
+    bic = R.resize(img, 3, 2 * n, R.BICUBIC, mapping=R.CORNER)[0, 1, :, 0]
+    for x in range(2 * n):
+        m = x // 2
+        if x % 2 == 0:
+            assert bil[x] == row[m] and bic[x] == row[m]
+        else:
+            assert bil[x] == (px(m) + px(m + 1)) / 2
+            assert abs(bic[x] - (-px(m - 1) + 9 * px(m) + 9 * px(m + 1) - px(m + 2)) / 16) < 1e-12
+
+
+@pytest.mark.parametrize("sizes", [(8, 8, 20, 20), (9, 7, 5, 13), (6, 6, 6, 6)])
+def test_paper_eq5_with_printed_map(sizes):
+    """Eqs. 1-5 evaluated as the paper writes them, pixel by pixel: x_p = x_f /
+    scale, P1 = (int x_p, int y_p), P2 its right, P3 its lower and P4 its
+    lower-right neighbour (clamped to the image), offsets the fractional
+    parts, and eq. 5 with (1 - offsetX) on P1 and P3."""
+    in_h, in_w, out_h, out_w = sizes
+    img = fields.uniform_u8((in_h, in_w), seed=in_h * 7 + in_w).astype(np.float64)
+    got = R.resize(img, out_h, out_w, R.BILINEAR, mapping=R.CORNER)[0, :, :, 0]
+    for yf in range(out_h):
+        for xf in range(out_w):
+            xp, yp = Fraction(xf * in_w, out_w), Fraction(yf * in_h, out_h)
+            x1, y1 = int(xp), int(yp)
+            ox, oy = xp - x1, yp - y1
+            x2, y2 = min(x1 + 1, in_w - 1), min(y1 + 1, in_h - 1)
+            p1, p2, p3, p4 = (Fraction(int(img[y1, x1])), Fraction(int(img[y1, x2])),
+                              Fraction(int(img[y2, x1])), Fraction(int(img[y2, x2])))
+            want = (1 - oy) * ((1 - ox) * p1 + ox * p2) + oy * ((1 - ox) * p3 + ox * p4)
+            assert abs(got[yf, xf] - float(want)) < 1e-12, (yf, xf)
+
+
 def test_pil_bicubic_interior():
     Image = pytest.importorskip("PIL.Image")
     for in_h, in_w, out_h, out_w in [(16, 16, 32, 32), (21, 13, 50, 37)]:
@@ -420,8 +497,8 @@ def test_needed_rows_cover_band():
 def _mutant_taps(kind):
     orig = R.axis_taps
 
-    def taps(n_in, n_out, filt, a=R.KEYS_A):
-        idx, w, x0, t = orig(n_in, n_out, filt, a)
+    def taps(n_in, n_out, filt, a=R.KEYS_A, mapping=R.HALF_PIXEL):
+        idx, w, x0, t = orig(n_in, n_out, filt, a, mapping)
         idx, w = idx.copy(), w.copy()
         if kind == "trunc":          # int() read as truncation toward zero
             s = R.source_coordinate(np.arange(n_out), n_in, n_out)
