@@ -318,7 +318,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
     dev = torch.device("cuda:0")
     out = {}
 
-    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None):
+    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel"):
         src0 = make_src()
         in_bytes = src0.numel() * src0.element_size()
         out_bytes = math.prod(out_shape) * src0.element_size()
@@ -335,7 +335,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         tile, _ = xr.autotune(srcs, dsts, mode, layout=layout, candidates=cands, reps=4, groups=3)
 
         def launch(i):
-            xr.resize_into(srcs[i], dsts[i], mode, layout=layout)
+            xr.resize_into(srcs[i], dsts[i], mode, layout=layout, mapping=mapping)
 
         wall, ms = time_launches(launch, n_buf, steps, warmup, torch)
         k_s = sum(ms) / len(ms) / 1e3
@@ -354,6 +354,9 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
     for dname, t in [("u8", u8), ("f16", unit.half()), ("f32", unit.float())]:
         for direction, n in [("x2", 8192), ("x0.5", 2048)]:
             measure(f"c2_bicubic_{direction}_{dname}_rgba", lambda t=t: t, (n, n, 4), "bicubic")
+    measure("nearest_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "nearest")
+    measure("bilinear_paper_map_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "bilinear", mapping="paper")
+    measure("bicubic_paper_map_x3_u8_rgba", lambda: u8, (12288, 12288, 4), "bicubic", mapping="paper")
     del fld, unit, u8
     measure("c1_bilinear_x2_u8_512", lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev),
             (1024, 1024), "bilinear")

@@ -6,6 +6,8 @@
  * Along each axis an output index x of an image resized from N_in to N_out
  * samples reads the source at the half-pixel coordinate
  *     s(x) = ((2x + 1) N_in - N_out) / (2 N_out)          (eq. 1)
+ * (xr_resize also offers eq. 1 as printed, s(x) = x N_in / N_out, and
+ * nearest neighbour)
  * with base tap x0 = floor(s) and offset t = s - x0        (eqs. 2-4)
  * evaluated from exact integers. Bilinear takes taps x0, x0+1 with weights
  * (1 - t, t); bicubic takes x0-1 .. x0+2 with the Keys (1981) cubic weights
@@ -60,6 +62,11 @@ extern "C" {
 
 #define XR_BILINEAR 0
 #define XR_BICUBIC 1
+#define XR_NEAREST 2        /* xr_resize only */
+
+/* coordinate maps of xr_resize (eq. 1) */
+#define XR_MAP_HALF_PIXEL 0 /* s = ((2x + 1) N_in - N_out) / (2 N_out): pixel centres aligned */
+#define XR_MAP_PAPER 1      /* s = x N_in / N_out: eq. 1 as printed, x_p = x_f / scale      */
 
 #define XR_MAX_SIDE 32768   /* largest width/height of any image (keeps (2x+1)N in int32) */
 
@@ -149,6 +156,26 @@ int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *
 int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream);
 
 /*
+ * Forward resize with a chosen filter and coordinate map.
+ *  filter  = XR_BILINEAR, XR_BICUBIC, or XR_NEAREST: one tap, the source
+ *            pixel whose area contains the mapped point, floor(s + 1/2) under
+ *            XR_MAP_HALF_PIXEL (pixel i covers [i - 1/2, i + 1/2)) and
+ *            floor(s) under XR_MAP_PAPER (pixel i covers [i, i + 1)); it
+ *            copies source values exactly. Nearest neighbour is one of the
+ *            interpolation methods section II of the paper names.
+ *  mapping = XR_MAP_HALF_PIXEL (as xr_resize_bilinear / _bicubic) or
+ *            XR_MAP_PAPER: s = x N_in / N_out, the map of eq. 1 as printed
+ *            (x_p = x_f / scale with scale = N_out / N_in from the sizes);
+ *            eqs. 2-5 then apply unchanged, taps clamped to the image.
+ * xr_resize(src, dst, XR_BILINEAR, XR_MAP_HALF_PIXEL, tile, stream) is
+ * xr_resize_bilinear(src, dst, tile, stream); likewise for bicubic. Same
+ * contract otherwise (bands: see xr_needed_rows_map). XR_ERR_ARG for an
+ * unknown filter or mapping.
+ */
+int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t mapping,
+              const xr_tile *tile, void *stream);
+
+/*
  * Batched resize of many images of uneven sizes and scales in ONE persistent
  * launch (the paper's per-image tiling question asked for a whole batch,
  * section III.B).
@@ -171,7 +198,7 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
 typedef struct {
     xr_image src;
     xr_image dst;
-    int32_t filter;    /* XR_BILINEAR or XR_BICUBIC */
+    int32_t filter;    /* XR_BILINEAR or XR_BICUBIC (pixel-centre map) */
 } xr_job;
 
 size_t xr_batch_workspace_bytes(int32_t n_jobs);
@@ -247,7 +274,8 @@ int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
  * xr_source_taps: for output index x of an axis n_in -> n_out, the base tap
  *   x0 = floor(s(x)) and the numerator / denominator of t = num/den (eqs. 1-4).
  * xr_needed_rows: inclusive range of clamped source rows that output rows
- *   [row0, row0 + rows) read.
+ *   [row0, row0 + rows) read (pixel-centre map; XR_BILINEAR or XR_BICUBIC).
+ * xr_needed_rows_map: the same for any filter of xr_resize and either map.
  * xr_thread_of_pixel: eq. 6 inverted for a tile shape: the workgroup
  *   (block_x, block_y) and the thread (thread_x, thread_y) that compute output
  *   pixel (px, py), plus the pixel's index within that thread's ppt_x x ppt_y
@@ -257,6 +285,8 @@ int xr_source_taps(int32_t n_in, int32_t n_out, int32_t x, int32_t *x0, int64_t 
                    int64_t *t_den);
 int xr_needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
                    int32_t *first, int32_t *last);
+int xr_needed_rows_map(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
+                       int32_t mapping, int32_t *first, int32_t *last);
 int xr_thread_of_pixel(const xr_tile *tile, int32_t px, int32_t py, int32_t *block_x,
                        int32_t *block_y, int32_t *thread_x, int32_t *thread_y, int32_t *sub_x,
                        int32_t *sub_y);

@@ -25,6 +25,9 @@ from ._lib import (  # noqa: F401
     XR_KERNEL_STRIP,
     XR_KERNEL_STRIP_ANY,
     XR_KERNEL_STRIP_LDS,
+    XR_MAP_HALF_PIXEL,
+    XR_MAP_PAPER,
+    XR_NEAREST,
     XR_U8,
     XResizeError,
     XrImage,
@@ -36,7 +39,8 @@ from ._lib import (  # noqa: F401
 )
 
 _DTYPES = {torch.uint8: XR_U8, torch.float16: XR_F16, torch.float32: XR_F32}
-_FILTERS = {"bilinear": XR_BILINEAR, "bicubic": XR_BICUBIC}
+_FILTERS = {"bilinear": XR_BILINEAR, "bicubic": XR_BICUBIC, "nearest": XR_NEAREST}
+_MAPPINGS = {"half_pixel": XR_MAP_HALF_PIXEL, "paper": XR_MAP_PAPER}
 
 
 def filter_code(mode) -> int:
@@ -45,7 +49,16 @@ def filter_code(mode) -> int:
     try:
         return _FILTERS[mode]
     except KeyError:
-        raise ValueError(f"mode must be 'bilinear' or 'bicubic', not {mode!r}") from None
+        raise ValueError(f"mode must be 'bilinear', 'bicubic' or 'nearest', not {mode!r}") from None
+
+
+def mapping_code(mapping) -> int:
+    if isinstance(mapping, int):
+        return mapping
+    try:
+        return _MAPPINGS[mapping]
+    except KeyError:
+        raise ValueError(f"mapping must be 'half_pixel' or 'paper', not {mapping!r}") from None
 
 
 def _stream_handle(t: torch.Tensor, stream=None):
@@ -107,17 +120,25 @@ def _tile_ptr(t):
 
 def resize_into(src: torch.Tensor, dst: torch.Tensor, mode="bilinear", layout="hwc", tile=None,
                 src_row0: int = 0, src_height: int | None = None, dst_row0: int = 0,
-                dst_height: int | None = None, stream=None) -> torch.Tensor:
-    """Resize ``src`` into the preallocated ``dst`` (both on the same GPU)."""
+                dst_height: int | None = None, stream=None, mapping="half_pixel") -> torch.Tensor:
+    """Resize ``src`` into the preallocated ``dst`` (both on the same GPU).
+    ``mode``: 'bilinear', 'bicubic' or 'nearest'; ``mapping``: 'half_pixel'
+    (pixel centres) or 'paper' (eq. 1 as printed, s = x * in / out)."""
     s = image(src, layout, src_row0, src_height)
     d = image(dst, layout, dst_row0, dst_height)
-    fn = lib.xr_resize_bicubic if filter_code(mode) == XR_BICUBIC else lib.xr_resize_bilinear
-    check(fn(ctypes.byref(s), ctypes.byref(d), _tile_ptr(tile), _stream_handle(src, stream)),
-          "resize")
+    f, m = filter_code(mode), mapping_code(mapping)
+    if m == XR_MAP_HALF_PIXEL and f != XR_NEAREST:
+        fn = lib.xr_resize_bicubic if f == XR_BICUBIC else lib.xr_resize_bilinear
+        rc = fn(ctypes.byref(s), ctypes.byref(d), _tile_ptr(tile), _stream_handle(src, stream))
+    else:
+        rc = lib.xr_resize(ctypes.byref(s), ctypes.byref(d), f, m, _tile_ptr(tile),
+                           _stream_handle(src, stream))
+    check(rc, "resize")
     return dst
 
 
-def resize(x: torch.Tensor, size, mode="bilinear", layout="hwc", tile=None, stream=None) -> torch.Tensor:
+def resize(x: torch.Tensor, size, mode="bilinear", layout="hwc", tile=None, stream=None,
+           mapping="half_pixel") -> torch.Tensor:
     """Resize to ``size = (out_h, out_w)``; returns a new tensor of x's dtype."""
     out_h, out_w = int(size[0]), int(size[1])
     if layout == "hwc":
@@ -130,7 +151,7 @@ def resize(x: torch.Tensor, size, mode="bilinear", layout="hwc", tile=None, stre
     else:
         shape = (x.shape[0], x.shape[1], out_h, out_w)
     out = torch.empty(shape, dtype=x.dtype, device=x.device)
-    return resize_into(x, out, mode, layout, tile, stream=stream)
+    return resize_into(x, out, mode, layout, tile, stream=stream, mapping=mapping)
 
 
 def resize_backward(grad_out: torch.Tensor, in_size, mode="bilinear", layout="nchw",
@@ -267,10 +288,10 @@ def source_taps(n_in: int, n_out: int, x: int):
     return x0.value, num.value, den.value
 
 
-def needed_rows(in_h: int, out_h: int, row0: int, rows: int, mode) -> tuple:
+def needed_rows(in_h: int, out_h: int, row0: int, rows: int, mode, mapping="half_pixel") -> tuple:
     first, last = ctypes.c_int32(), ctypes.c_int32()
-    check(lib.xr_needed_rows(in_h, out_h, row0, rows, filter_code(mode), ctypes.byref(first),
-                             ctypes.byref(last)), "needed_rows")
+    check(lib.xr_needed_rows_map(in_h, out_h, row0, rows, filter_code(mode), mapping_code(mapping),
+                                 ctypes.byref(first), ctypes.byref(last)), "needed_rows")
     return first.value, last.value
 
 

@@ -27,7 +27,8 @@ XR_ERR_HIP = 10
 XR_ERR_ARG = 11
 
 XR_U8, XR_F16, XR_F32 = 0, 1, 2
-XR_BILINEAR, XR_BICUBIC = 0, 1
+XR_BILINEAR, XR_BICUBIC, XR_NEAREST = 0, 1, 2
+XR_MAP_HALF_PIXEL, XR_MAP_PAPER = 0, 1
 XR_MAX_SIDE = 32768
 XR_KERNEL_AUTO, XR_KERNEL_GATHER, XR_KERNEL_STRIP, XR_KERNEL_STRIP_ANY, XR_KERNEL_STRIP_LDS = 0, 1, 2, 3, 4
 
@@ -87,6 +88,7 @@ def _load():
     sigs = {
         "xr_resize_bilinear": (ctypes.c_int, [pimg, pimg, ptile, vp]),
         "xr_resize_bicubic": (ctypes.c_int, [pimg, pimg, ptile, vp]),
+        "xr_resize": (ctypes.c_int, [pimg, pimg, i32, i32, ptile, vp]),
         "xr_batch_workspace_bytes": (sz, [i32]),
         "xr_batch_prepare": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, vp, sz, vp]),
         "xr_resize_batched": (ctypes.c_int, [vp, i32, vp]),
@@ -100,6 +102,7 @@ def _load():
         "xr_set_tile": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, i32, ptile]),
         "xr_source_taps": (ctypes.c_int, [i32, i32, i32, pi32, pi64, pi64]),
         "xr_needed_rows": (ctypes.c_int, [i32, i32, i32, i32, i32, pi32, pi32]),
+        "xr_needed_rows_map": (ctypes.c_int, [i32, i32, i32, i32, i32, i32, pi32, pi32]),
         "xr_thread_of_pixel": (ctypes.c_int, [ptile, i32, i32, pi32, pi32, pi32, pi32, pi32, pi32]),
         "xr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "xr_last_error": (ctypes.c_char_p, []),

@@ -61,20 +61,34 @@ int64_t floor_div(int64_t a, int64_t b)
     return q;
 }
 
-// x0 = floor(s(x)) for s(x) = ((2x+1) n_in - n_out) / (2 n_out)
-int64_t base_tap(int64_t x, int64_t n_in, int64_t n_out)
+bool valid_filter(int32_t filter)
 {
-    return floor_div((2 * x + 1) * n_in - n_out, 2 * n_out);
+    return filter == XR_BILINEAR || filter == XR_BICUBIC || filter == XR_NEAREST;
+}
+bool valid_mapping(int32_t mapping) { return mapping == XR_MAP_HALF_PIXEL || mapping == XR_MAP_PAPER; }
+
+// Base tap of output index x (eqs. 1-4) with o = 1 for pixel centres,
+// s(x) = ((2x+1) n_in - n_out) / (2 n_out), and o = 0 for the printed map,
+// s(x) = x n_in / n_out: x0 = floor(s(x)); for nearest neighbour the pixel
+// whose area holds the point, floor((2x+o) n_in / (2 n_out)).
+int64_t base_tap(int64_t x, int64_t n_in, int64_t n_out, int32_t filter = XR_BILINEAR,
+                 int32_t mapping = XR_MAP_HALF_PIXEL)
+{
+    const int64_t o = mapping == XR_MAP_HALF_PIXEL ? 1 : 0;
+    if (filter == XR_NEAREST)
+        return floor_div((2 * x + o) * n_in, 2 * n_out);
+    return floor_div((2 * x + o) * n_in - o * n_out, 2 * n_out);
 }
 
-int taps_of(int32_t filter) { return filter == XR_BICUBIC ? 4 : 2; }
+int taps_of(int32_t filter) { return filter == XR_BICUBIC ? 4 : (filter == XR_NEAREST ? 1 : 2); }
 int first_offset(int32_t filter) { return filter == XR_BICUBIC ? -1 : 0; }
 
 void needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
-                 int32_t *first, int32_t *last)
+                 int32_t *first, int32_t *last, int32_t mapping = XR_MAP_HALF_PIXEL)
 {
-    const int64_t lo = base_tap(row0, in_h, out_h) + first_offset(filter);
-    const int64_t hi = base_tap(row0 + rows - 1, in_h, out_h) + first_offset(filter) + taps_of(filter) - 1;
+    const int64_t lo = base_tap(row0, in_h, out_h, filter, mapping) + first_offset(filter);
+    const int64_t hi = base_tap(row0 + rows - 1, in_h, out_h, filter, mapping) + first_offset(filter) +
+                       taps_of(filter) - 1;
     *first = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(lo, 0), in_h - 1));
     *last = static_cast<int32_t>(std::min<int64_t>(std::max<int64_t>(hi, 0), in_h - 1));
 }
@@ -135,10 +149,13 @@ bool overlaps(const xr_image &a, const xr_image &b)
     return a0 < b1 && b0 < a1;
 }
 
-int check_pair(const xr_image *src, const xr_image *dst, int32_t filter)
+int check_pair(const xr_image *src, const xr_image *dst, int32_t filter,
+               int32_t mapping = XR_MAP_HALF_PIXEL)
 {
-    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
-        return fail(XR_ERR_ARG, "filter = %d is not XR_BILINEAR or XR_BICUBIC", filter);
+    if (!valid_filter(filter))
+        return fail(XR_ERR_ARG, "filter = %d is not XR_BILINEAR, XR_BICUBIC or XR_NEAREST", filter);
+    if (!valid_mapping(mapping))
+        return fail(XR_ERR_ARG, "mapping = %d is not XR_MAP_HALF_PIXEL or XR_MAP_PAPER", mapping);
     int rc = check_image(src, "src");
     if (rc)
         return rc;
@@ -153,7 +170,7 @@ int check_pair(const xr_image *src, const xr_image *dst, int32_t filter)
     if (src->planes != dst->planes)
         return fail(XR_ERR_SHAPE, "src.planes %d != dst.planes %d", src->planes, dst->planes);
     int32_t first, last;
-    needed_rows(src->height, dst->height, dst->row0, dst->rows, filter, &first, &last);
+    needed_rows(src->height, dst->height, dst->row0, dst->rows, filter, &first, &last, mapping);
     if (first < src->row0 || last > src->row0 + src->rows - 1)
         return fail(XR_ERR_RANGE, "output rows [%d, %d) read source rows %d..%d but src holds [%d, %d)",
                     dst->row0, dst->row0 + dst->rows, first, last, src->row0,
@@ -172,7 +189,7 @@ bool src_aligned4(const xr_image &src)
            (src.planes == 1 || src.plane_pitch % 4 == 0) && row_bytes % 4 == 0;
 }
 
-xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
+xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst, int32_t mapping = XR_MAP_HALF_PIXEL)
 {
     xr::ResizeArgs a{};
     a.src = static_cast<const unsigned char *>(src.data);
@@ -195,12 +212,15 @@ xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst)
     };
     a.aligned16 = al(src.data, a.src_pitch, a.src_plane_pitch) && al(dst.data, a.dst_pitch, a.dst_plane_pitch);
     a.aligned4 = src_aligned4(src);
+    a.map_off = mapping == XR_MAP_HALF_PIXEL ? 1 : 0;
     return a;
 }
 
-int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t)
+// The exact x2 and x0.5 walks assume pixel centres and 2 or 4 taps.
+int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t, int32_t filter,
+                  int32_t mapping)
 {
-    if (t.kernel != XR_KERNEL_STRIP)
+    if (t.kernel != XR_KERNEL_STRIP || mapping != XR_MAP_HALF_PIXEL || filter == XR_NEAREST)
         return xr::kGeneral;
     if (dst.width == 2 * src.width && dst.height == 2 * src.height)
         return xr::kUp2;
@@ -382,9 +402,9 @@ int check_grid(const xr_tile &t, const xr_image &dst)
 }
 
 int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile, int32_t filter,
-                  void *stream)
+                  int32_t mapping, void *stream)
 {
-    int rc = check_pair(src, dst, filter);
+    int rc = check_pair(src, dst, filter, mapping);
     if (rc)
         return rc;
     const xr_tile t = resolve_tile(tile, filter, *src, *dst);
@@ -397,9 +417,10 @@ int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile,
     rc = check_lds(t, filter, src->dtype, src->channels, src->width, dst->width, src_aligned4(*src));
     if (rc)
         return rc;
-    const xr::ResizeArgs a = make_args(*src, *dst);
+    const xr::ResizeArgs a = make_args(*src, *dst, mapping);
     const hipError_t e = xr::launch_forward(a, filter, src->dtype, src->channels, t,
-                                            axis_mode(*src, *dst, t), static_cast<hipStream_t>(stream));
+                                            axis_mode(*src, *dst, t, filter, mapping),
+                                            static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "resize launch");
     return XR_OK;
@@ -433,12 +454,18 @@ extern "C" {
 
 int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
 {
-    return resize_common(src, dst, tile, XR_BILINEAR, stream);
+    return resize_common(src, dst, tile, XR_BILINEAR, XR_MAP_HALF_PIXEL, stream);
 }
 
 int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
 {
-    return resize_common(src, dst, tile, XR_BICUBIC, stream);
+    return resize_common(src, dst, tile, XR_BICUBIC, XR_MAP_HALF_PIXEL, stream);
+}
+
+int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t mapping,
+              const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, filter, mapping, stream);
 }
 
 size_t xr_batch_workspace_bytes(int32_t n_jobs)
@@ -480,6 +507,8 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
         const int rc = check_pair(&jobs[k].src, &jobs[k].dst, jobs[k].filter);
         if (rc)
             return fail(rc, "job %d: %s", k, g_last_error.c_str());
+        if (jobs[k].filter == XR_NEAREST)
+            return fail(XR_ERR_ARG, "job %d: the batched launch takes XR_BILINEAR or XR_BICUBIC", k);
         if (jobs[k].src.dtype != dtype)
             return fail(XR_ERR_DTYPE, "job %d: dtype %d differs from job 0 (%d)", k, jobs[k].src.dtype,
                         dtype);
@@ -838,7 +867,7 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
     bool have = false;
     std::vector<float> per_group(groups);
     for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
-        const int32_t mode = axis_mode(*src, *dst, cand[k]);
+        const int32_t mode = axis_mode(*src, *dst, cand[k], filter, XR_MAP_HALF_PIXEL);
         e = launch(cand[k], mode);  // warm-up
         for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
             e = hipEventRecord(ev0, s);
@@ -886,7 +915,7 @@ int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
 {
     if (!out)
         return fail(XR_ERR_NULL, "out is NULL");
-    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+    if (!valid_filter(filter))
         return fail(XR_ERR_ARG, "filter = %d unknown", filter);
     if (elem_size(dtype) == 0)
         return fail(XR_ERR_DTYPE, "dtype = %d unknown", dtype);
@@ -906,7 +935,7 @@ int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
 {
     if (!tile)
         return fail(XR_ERR_NULL, "tile is NULL");
-    if (filter != XR_BILINEAR && filter != XR_BICUBIC)
+    if (!valid_filter(filter))
         return fail(XR_ERR_ARG, "filter = %d unknown", filter);
     if (elem_size(dtype) == 0)
         return fail(XR_ERR_DTYPE, "dtype = %d unknown", dtype);
@@ -944,6 +973,23 @@ int xr_source_taps(int32_t n_in, int32_t n_out, int32_t x, int32_t *x0, int64_t 
     *x0 = static_cast<int32_t>(q);
     *t_num = num - q * den;
     *t_den = den;
+    return XR_OK;
+}
+
+int xr_needed_rows_map(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
+                       int32_t mapping, int32_t *first, int32_t *last)
+{
+    if (!first || !last)
+        return fail(XR_ERR_NULL, "output pointer is NULL");
+    if (!valid_filter(filter))
+        return fail(XR_ERR_ARG, "filter = %d unknown", filter);
+    if (!valid_mapping(mapping))
+        return fail(XR_ERR_ARG, "mapping = %d unknown", mapping);
+    if (in_h < 1 || out_h < 1 || in_h > XR_MAX_SIDE || out_h > XR_MAX_SIDE)
+        return fail(XR_ERR_SHAPE, "sizes %d -> %d outside 1..%d", in_h, out_h, XR_MAX_SIDE);
+    if (rows < 1 || row0 < 0 || static_cast<int64_t>(row0) + rows > out_h)
+        return fail(XR_ERR_RANGE, "rows [%d, %d) outside [0, %d)", row0, row0 + rows, out_h);
+    needed_rows(in_h, out_h, row0, rows, filter, first, last, mapping);
     return XR_OK;
 }
 

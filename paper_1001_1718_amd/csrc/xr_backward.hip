@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
     for (int32_t k = tid; k < nrows; k += kBwdThreads) {
         int32_t y0;
         float t, omt;
-        axis_tap(ya + k, a.in_h, a.out_h, y0, t, omt);
+        axis_tap(ya + k, a.in_h, a.out_h, 1, y0, t, omt);
         float w[K];
         weights<FILTER>(t, omt, w);
         ylo[k] = y0 + TP::LO;
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
             const int32_t x = min(xc + p, xb);
             int32_t x0;
             float t, omt;
-            axis_tap(x, a.in_w, a.out_w, x0, t, omt);
+            axis_tap(x, a.in_w, a.out_w, 1, x0, t, omt);
             weights<FILTER>(t, omt, wx[p]);
 #pragma unroll
             for (int i = 0; i < K; ++i) {
@@ -370,14 +370,14 @@ __global__ void __launch_bounds__(256) k_bwd_up2_border(ResizeArgs a)
     for (int32_t y = y_lo; y <= y_hi; ++y) {
         int32_t y0;
         float ty, uy;
-        axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+        axis_tap(y, a.in_h, a.out_h, 1, y0, ty, uy);
         float wy[K];
         weights<FILTER>(ty, uy, wy);
         const unsigned char *grow = gsrc + static_cast<int64_t>(y) * a.src_pitch;
         for (int32_t x = x_lo; x <= x_hi; ++x) {
             int32_t x0;
             float tx, ux;
-            axis_tap(x, a.in_w, a.out_w, x0, tx, ux);
+            axis_tap(x, a.in_w, a.out_w, 1, x0, tx, ux);
             float wx[K];
             weights<FILTER>(tx, ux, wx);
             float w = 0.0f;

@@ -17,22 +17,25 @@ namespace dev {
 
 constexpr int kBilinear = 0;
 constexpr int kBicubic = 1;
+constexpr int kNearest = 2;
 
 template <int FILTER>
 struct Taps {
-    static constexpr int K = (FILTER == kBicubic) ? 4 : 2;  // taps per axis
+    static constexpr int K = (FILTER == kBicubic) ? 4 : (FILTER == kNearest ? 1 : 2);  // taps per axis
     static constexpr int LO = (FILTER == kBicubic) ? -1 : 0;  // first tap relative to x0
 };
 
-// Eqs. 1-4 with half-pixel centres: s = ((2x+1) n_in - n_out) / (2 n_out),
-// x0 = floor(s), t = s - x0 and omt = 1 - t. The numerator fits in int32 for
-// sides up to 32768; t and 1 - t are each one correctly rounded division of
-// two exact integers, so both carry a relative error of at most half an ulp
-// (1 - t is not formed by a subtraction that would cancel as t -> 1).
-__device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out, int32_t &x0,
-                                         float &t, float &omt)
+// Eqs. 1-4: s = ((2x+o) n_in - o n_out) / (2 n_out), with o = 1 for pixel
+// centres (s = (x + 1/2) n_in / n_out - 1/2) and o = 0 for the map as eq. 1
+// prints it (s = x n_in / n_out); x0 = floor(s), t = s - x0, omt = 1 - t.
+// The numerator fits in int32 for sides up to 32768; t and 1 - t are each one
+// correctly rounded division of two exact integers, so both carry a relative
+// error of at most half an ulp (1 - t is not formed by a subtraction that
+// would cancel as t -> 1).
+__device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out, int32_t o,
+                                         int32_t &x0, float &t, float &omt)
 {
-    const int32_t num = (2 * x + 1) * n_in - n_out;
+    const int32_t num = (2 * x + o) * n_in - o * n_out;
     const int32_t den = 2 * n_out;
     int32_t q = num / den;
     int32_t rem = num - q * den;
@@ -45,6 +48,24 @@ __device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out,
     omt = __fdiv_rn(static_cast<float>(den - rem), static_cast<float>(den));
 }
 
+// The tap of FILTER for output x: eqs. 1-4 for bilinear and bicubic; for
+// nearest neighbour the source pixel whose area contains the mapped point,
+// floor(s + o/2) = floor((2x+o) n_in / (2 n_out)) (pixel i covers
+// [i - 1/2, i + 1/2) with pixel centres, [i, i + 1) with the printed map),
+// with weight 1.
+template <int FILTER>
+__device__ __forceinline__ void source_tap(int32_t x, int32_t n_in, int32_t n_out, int32_t o,
+                                           int32_t &x0, float &t, float &omt)
+{
+    if constexpr (FILTER == kNearest) {
+        x0 = ((2 * x + o) * n_in) / (2 * n_out);  // non-negative: division is floor
+        t = 0.0f;
+        omt = 1.0f;
+    } else {
+        axis_tap(x, n_in, n_out, o, x0, t, omt);
+    }
+}
+
 // Bilinear weights (1 - t, t) for taps x0, x0+1 (eq. 5).
 // Keys cubic weights for a = -1/2 at taps x0-1 .. x0+2, i.e. K(t+1), K(t),
 // K(1-t), K(2-t), written in factored forms whose every factor is computed
@@ -54,7 +75,11 @@ __device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out,
 template <int FILTER>
 __device__ __forceinline__ void weights(float t, float omt, float (&w)[Taps<FILTER>::K])
 {
-    if constexpr (FILTER == kBilinear) {
+    if constexpr (FILTER == kNearest) {
+        (void)t;
+        (void)omt;
+        w[0] = 1.0f;
+    } else if constexpr (FILTER == kBilinear) {
         w[0] = omt;
         w[1] = t;
     } else {

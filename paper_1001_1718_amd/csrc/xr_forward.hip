@@ -87,8 +87,8 @@ __global__ void __launch_bounds__(1024) k_gather(ResizeArgs a)
     const int32_t plane = blockIdx.z;
     int32_t x0, y0;
     float tx, ty, ux, uy;
-    axis_tap(px, a.in_w, a.out_w, x0, tx, ux);
-    axis_tap(a.dst_row0 + py, a.in_h, a.out_h, y0, ty, uy);
+    source_tap<FILTER>(px, a.in_w, a.out_w, a.map_off, x0, tx, ux);
+    source_tap<FILTER>(a.dst_row0 + py, a.in_h, a.out_h, a.map_off, y0, ty, uy);
     float wx[K], wy[K];
     weights<FILTER>(tx, ux, wx);
     weights<FILTER>(ty, uy, wy);
@@ -203,7 +203,7 @@ struct StripBody {
             const int32_t x = min(col0 + c, a.out_w - 1);
             int32_t x0;
             float t, u;
-            axis_tap(x, a.in_w, a.out_w, x0, t, u);
+            source_tap<FILTER>(x, a.in_w, a.out_w, a.map_off, x0, t, u);
             weights<FILTER>(t, u, wx[c]);
 #pragma unroll
             for (int i = 0; i < K; ++i)
@@ -217,8 +217,8 @@ struct StripBody {
         const int32_t y_end = a.dst_row0 + r_end;
         int32_t y0, y0_last;
         float ty, uy, tl, ul;
-        axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
-        axis_tap(y_end - 1, a.in_h, a.out_h, y0_last, tl, ul);
+        source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
+        source_tap<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, y0_last, tl, ul);
         float wy[K];
         weights<FILTER>(ty, uy, wy);
         int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
@@ -242,7 +242,7 @@ struct StripBody {
                 }
                 ++y;
                 if (y < y_end) {
-                    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+                    source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
                     weights<FILTER>(ty, uy, wy);
                     last = y0 + TP::LO + K - 1;
                 }
@@ -383,8 +383,8 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
     // chunk-aligned byte seg_b0 on
     int32_t xa, xb;
     float tq, uq;
-    axis_tap(c_first, a.in_w, a.out_w, xa, tq, uq);
-    axis_tap(c_last, a.in_w, a.out_w, xb, tq, uq);
+    source_tap<FILTER>(c_first, a.in_w, a.out_w, a.map_off, xa, tq, uq);
+    source_tap<FILTER>(c_last, a.in_w, a.out_w, a.map_off, xb, tq, uq);
     const int32_t seg0 = clampi(xa + TP::LO, 0, a.in_w - 1);
     const int32_t seg1 = clampi(xb + TP::LO + K - 1, 0, a.in_w - 1);
     const int32_t seg_b0 = (seg0 * PB) & ~(CB - 1);
@@ -398,7 +398,7 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
         const int32_t x = min(col0 + c, a.out_w - 1);
         int32_t x0;
         float t, u;
-        axis_tap(x, a.in_w, a.out_w, x0, t, u);
+        source_tap<FILTER>(x, a.in_w, a.out_w, a.map_off, x0, t, u);
         weights<FILTER>(t, u, wx[c]);
 #pragma unroll
         for (int i = 0; i < K; ++i)
@@ -412,8 +412,8 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
     const int32_t y_end = a.dst_row0 + r_end;
     int32_t y0, y0_last;
     float ty, uy, tl, ul;
-    axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
-    axis_tap(y_end - 1, a.in_h, a.out_h, y0_last, tl, ul);
+    source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
+    source_tap<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, y0_last, tl, ul);
     float wy[K];
     weights<FILTER>(ty, uy, wy);
     int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
             }
             ++y;
             if (y < y_end) {
-                axis_tap(y, a.in_h, a.out_h, y0, ty, uy);
+                source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
                 weights<FILTER>(ty, uy, wy);
                 last = y0 + TP::LO + K - 1;
             }
@@ -1025,9 +1025,11 @@ bool lds_fits_filter(int32_t dtype, int32_t channels, int32_t in_w, int32_t out_
 bool strip_lds_fits(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w,
                     int32_t block_w, bool aligned4)
 {
-    return filter == XR_BICUBIC
-               ? lds_fits_filter<kBicubic>(dtype, channels, in_w, out_w, block_w, aligned4)
-               : lds_fits_filter<kBilinear>(dtype, channels, in_w, out_w, block_w, aligned4);
+    if (filter == XR_BICUBIC)
+        return lds_fits_filter<kBicubic>(dtype, channels, in_w, out_w, block_w, aligned4);
+    if (filter == XR_NEAREST)
+        return lds_fits_filter<kNearest>(dtype, channels, in_w, out_w, block_w, aligned4);
+    return lds_fits_filter<kBilinear>(dtype, channels, in_w, out_w, block_w, aligned4);
 }
 
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
@@ -1090,17 +1092,22 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
     const dim3 block(tile.block_w, tile.block_h, 1);
     const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
                     (a.dst_rows + rows_per_block - 1) / rows_per_block, a.planes);
-#define XR_STRIP_CASE(P)                                                                    \
-    case P:                                                                                 \
-        if (mode == kUp2)                                                                   \
-            hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,   \
-                               tile.ppt_y, tile.order);                                     \
-        else if (mode == kDown2)                                                            \
-            hipLaunchKernelGGL((k_strip_down2<FILTER, T, C, P>), grid, block, 0, stream, a, \
-                               tile.ppt_y, tile.order);                                     \
-        else                                                                                \
-            hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a,       \
-                               tile.ppt_y, tile.order);                                     \
+#define XR_STRIP_CASE(P)                                                                        \
+    case P:                                                                                     \
+        if constexpr (FILTER != kNearest) {                                                     \
+            if (mode == kUp2) {                                                                 \
+                hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,   \
+                                   tile.ppt_y, tile.order);                                     \
+                return hipGetLastError();                                                       \
+            }                                                                                   \
+            if (mode == kDown2) {                                                               \
+                hipLaunchKernelGGL((k_strip_down2<FILTER, T, C, P>), grid, block, 0, stream, a, \
+                                   tile.ppt_y, tile.order);                                     \
+                return hipGetLastError();                                                       \
+            }                                                                                   \
+        }                                                                                       \
+        hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a, tile.ppt_y,   \
+                           tile.order);                                                         \
         return hipGetLastError();
     if constexpr (C == 4) {
         switch (tile.ppt_x) {
@@ -1148,6 +1155,8 @@ hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, in
 {
     if (filter == XR_BICUBIC)
         return launch_filter<kBicubic>(a, dtype, channels, tile, mode, stream);
+    if (filter == XR_NEAREST)
+        return launch_filter<kNearest>(a, dtype, channels, tile, mode, stream);
     return launch_filter<kBilinear>(a, dtype, channels, tile, mode, stream);
 }
 

@@ -26,6 +26,7 @@ struct ResizeArgs {
     int32_t aligned16;       // src, dst and pitches are 16-byte aligned
     int32_t aligned4;        // src and its pitches are 4-byte aligned and a
                              // source row is a whole number of 4-byte words
+    int32_t map_off;         // 1: pixel-centre map; 0: the map eq. 1 prints
 };
 
 // Entry of the device job table of the batched launch.

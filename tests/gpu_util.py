@@ -23,7 +23,7 @@ F16_MAX_ABS = 1e-3
 F32_REL = 1e-5
 
 
-def is_dyadic_ratio(n_in: int, n_out: int) -> bool:
+def is_dyadic_ratio(n_in: int, n_out: int, mapping: int = R.HALF_PIXEL) -> bool:
     """True when every offset t of the axis is a multiple of 1/4.
 
     Then the bilinear weights are multiples of 1/4 and the Keys weights
@@ -32,8 +32,11 @@ def is_dyadic_ratio(n_in: int, n_out: int) -> bool:
     exact one, so its rounding must match the oracle's everywhere.
     """
     x = np.arange(n_out, dtype=np.int64)
-    rem = ((2 * x + 1) * n_in - n_out) % (2 * n_out)
-    return bool(np.all((4 * rem) % (2 * n_out) == 0))
+    if mapping == R.HALF_PIXEL:
+        rem, den = ((2 * x + 1) * n_in - n_out) % (2 * n_out), 2 * n_out
+    else:
+        rem, den = (x * n_in) % n_out, n_out
+    return bool(np.all((4 * rem) % den == 0))
 
 
 def check_u8(gpu: np.ndarray, ref: np.ndarray, exact: bool, what: str = ""):
@@ -76,9 +79,14 @@ def check_f32(gpu: np.ndarray, ref: np.ndarray, scale: np.ndarray, what: str = "
 
 
 def compare(gpu: np.ndarray, src_np: np.ndarray, out_h: int, out_w: int, filt: int, rows=None,
-            what: str = "", use_c: bool = True):
-    """Compare GPU output rows (P, R, W, C) with the oracle on the same rows."""
+            what: str = "", use_c: bool = True, mapping: int = R.HALF_PIXEL):
+    """Compare GPU output rows (P, R, W, C) with the oracle on the same rows.
+    Nearest neighbour copies source values, so it must match exactly in every
+    storage type; the C oracle covers the pixel-centre map with 2 or 4 taps."""
     from oracle import ref_c
+
+    if mapping != R.HALF_PIXEL or filt == R.NEAREST:
+        use_c = False
 
     planes = src_np if src_np.ndim == 4 else (src_np[None] if src_np.ndim == 3 else src_np[None, :, :, None])
     in_h, in_w = planes.shape[1], planes.shape[2]
@@ -90,11 +98,16 @@ def compare(gpu: np.ndarray, src_np: np.ndarray, out_h: int, out_w: int, filt: i
     elif gpu.ndim == 3:
         gpu = gpu[None]
     ref = (ref_c.resize_rows(planes, out_h, out_w, rows, filt) if use_c
-           else R.resize_rows(planes, out_h, out_w, rows, filt))
+           else R.resize_rows(planes, out_h, out_w, rows, filt, mapping=mapping))
+    if filt == R.NEAREST:
+        want = ref.astype(planes.dtype)
+        np.testing.assert_array_equal(np.asarray(gpu).reshape(want.shape).view(np.uint8),
+                                      want.view(np.uint8), err_msg=f"{what}: nearest is not an exact copy")
+        return 0
     if planes.dtype == np.uint8:
-        exact = is_dyadic_ratio(in_w, out_w) and is_dyadic_ratio(in_h, out_h)
+        exact = is_dyadic_ratio(in_w, out_w, mapping) and is_dyadic_ratio(in_h, out_h, mapping)
         return check_u8(gpu, ref, exact, what)
     if planes.dtype == np.float16:
         return check_f16(gpu, ref, what)
-    scale = R.resize_rows(planes, out_h, out_w, rows, filt, absolute=True)
+    scale = R.resize_rows(planes, out_h, out_w, rows, filt, absolute=True, mapping=mapping)
     return check_f32(gpu, ref, scale, what)

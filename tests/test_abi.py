@@ -173,6 +173,29 @@ def test_batch_validation():
     assert lib.xr_resize_batched(ws + 4096 * 256, 2, None) == 8  # never prepared
 
 
+def test_resize_with_mapping_validates_first():
+    f = _lib.lib.xr_resize
+    s, d = _img(), _img(32, 32, data=D2)
+    assert f(ctypes.byref(s), ctypes.byref(d), 3, 0, None, None) == 11   # unknown filter
+    assert f(ctypes.byref(s), ctypes.byref(d), 2, 2, None, None) == 11   # unknown mapping
+    assert f(None, ctypes.byref(d), 2, 1, None, None) == 1
+
+
+@pytest.mark.parametrize("filt", [0, 1, 2])
+@pytest.mark.parametrize("mapping", [0, 1])
+def test_needed_rows_map_match_oracle(filt, mapping):
+    from oracle import ref_resize as R
+
+    for in_h, out_h in [(17, 40), (40, 17), (9, 9), (1, 5), (300, 71)]:
+        for row0, rows in [(0, 1), (0, out_h), (out_h // 3, max(1, out_h // 4)), (out_h - 1, 1)]:
+            first, last = ctypes.c_int32(), ctypes.c_int32()
+            assert _lib.lib.xr_needed_rows_map(in_h, out_h, row0, rows, filt, mapping, ctypes.byref(first),
+                                               ctypes.byref(last)) == 0
+            assert (first.value, last.value) == R.needed_rows(in_h, out_h, row0, rows, filt, mapping)
+    first, last = ctypes.c_int32(), ctypes.c_int32()
+    assert _lib.lib.xr_needed_rows_map(8, 8, 0, 1, filt, 5, ctypes.byref(first), ctypes.byref(last)) == 11
+
+
 def test_strerror_all_codes():
     for code in range(12):
         assert _lib.strerror(code) and _lib.strerror(code) != "unknown error code"

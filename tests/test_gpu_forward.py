@@ -21,7 +21,8 @@ from gpu_util import compare  # noqa: E402
 from synth import fields  # noqa: E402
 
 DEV = "cuda:0"
-MODES = {"bilinear": 0, "bicubic": 1}
+MODES = {"bilinear": 0, "bicubic": 1, "nearest": 2}
+R_MAP = {"half_pixel": 0, "paper": 1}
 
 TILES = {
     "auto": None,
@@ -117,6 +118,67 @@ def test_small_all_kernels(shape, dtype, channels, mode):
     for name, o in outs.items():
         np.testing.assert_array_equal(o.view(np.uint8), outs["auto"].view(np.uint8),
                                       err_msg=f"kernel {name} differs from the default")
+
+
+MAP_SHAPES = [
+    ((37, 53), (74, 106)),   # x2: the printed map gives t in {0, 1/2}
+    ((37, 53), (61, 29)),    # non-dyadic up / down
+    ((64, 96), (32, 48)),    # x0.5
+    ((150, 70), (41, 263)),  # several tiles, mixed
+    ((1, 5), (3, 7)),        # one-row source
+]
+MODES_MAPS = [("nearest", "half_pixel"), ("nearest", "paper"), ("bilinear", "paper"),
+              ("bicubic", "paper")]
+
+
+@pytest.mark.parametrize("shape", MAP_SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
+@pytest.mark.parametrize("dtype", [np.uint8, np.float16, np.float32], ids=["u8", "f16", "f32"])
+@pytest.mark.parametrize("channels", [1, 4])
+@pytest.mark.parametrize("mode_map", MODES_MAPS, ids=lambda m: f"{m[0]}-{m[1]}")
+def test_nearest_and_printed_map(shape, dtype, channels, mode_map):
+    """Nearest neighbour and eq. 1 as printed, every kernel kind: bitwise equal
+    to each other and within the storage rule of the FP64 oracle (nearest:
+    exact copies)."""
+    mode, mapping = mode_map
+    (in_h, in_w), (out_h, out_w) = shape
+    img = _input(dtype, in_h, in_w, channels, seed=in_h * 1000 + in_w + channels + 7)
+    x = torch.from_numpy(img).to(DEV)
+    outs = {}
+    for name in TILES:
+        t = _tile_for(name, channels)
+        if name.startswith("strip_lds") and not _lds_stageable(t, in_w, out_w, mode, dtype, channels):
+            continue
+        y = xr.resize(x, (out_h, out_w), mode, tile=t, mapping=mapping)
+        torch.cuda.synchronize()
+        outs[name] = y.cpu().numpy()
+    m = R_MAP[mapping]
+    compare(outs["auto"], img, out_h, out_w, MODES[mode], what=f"{shape} {mode} {mapping}", mapping=m)
+    for name, o in outs.items():
+        np.testing.assert_array_equal(o.view(np.uint8), outs["auto"].view(np.uint8),
+                                      err_msg=f"kernel {name} differs from the default")
+
+
+@pytest.mark.parametrize("mode", ["nearest", "bilinear", "bicubic"])
+def test_printed_map_bands_match_whole_image(mode):
+    img = fields.field_unit(41, 30, 1, seed=8, dtype=np.float32)[:, :, 0]
+    out_h, out_w = 97, 50
+    whole = _gpu_map(img, out_h, out_w, mode, "paper")
+    x = torch.from_numpy(img).to(DEV)
+    bands = []
+    for row0, row1 in [(0, 30), (30, 31), (31, 97)]:
+        first, last = xr.needed_rows(41, out_h, row0, row1 - row0, mode, mapping="paper")
+        dst = torch.empty((row1 - row0, out_w), dtype=x.dtype, device=DEV)
+        xr.resize_into(x[first:last + 1].contiguous(), dst, mode, src_row0=first, src_height=41,
+                       dst_row0=row0, dst_height=out_h, mapping="paper")
+        bands.append(dst)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(torch.cat(bands).cpu().numpy().view(np.uint32), whole.view(np.uint32))
+
+
+def _gpu_map(src_np, out_h, out_w, mode, mapping):
+    y = xr.resize(torch.from_numpy(src_np).to(DEV), (out_h, out_w), mode, mapping=mapping)
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
 
 
 LDS_CASES = [
