@@ -68,8 +68,58 @@ __device__ __forceinline__ void store_raw(unsigned char *p, const RawBuf<BYTES, 
     *reinterpret_cast<RawBuf<BYTES, ALIGN> *>(__builtin_assume_aligned(p, ALIGN)) = v;
 }
 
+// Store of an output run that is written once and not read back by this
+// launch: non-temporal vector stores (they do not keep the lines in the
+// caches, which leaves room there for the source rows that neighbouring
+// strips re-read; measured faster for the x2 walk).
+template <int BYTES, int ALIGN>
+__device__ __forceinline__ void store_stream(unsigned char *p, const RawBuf<BYTES, ALIGN> &v)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    if constexpr (ALIGN >= 16 && BYTES % 16 == 0) {
+#pragma unroll
+        for (int i = 0; i < BYTES / 16; ++i)
+            __builtin_nontemporal_store(*reinterpret_cast<const u32x4 *>(v.b + 16 * i),
+                                        reinterpret_cast<u32x4 *>(__builtin_assume_aligned(p, 16)) + i);
+    } else if constexpr (ALIGN >= 8 && BYTES % 8 == 0) {
+#pragma unroll
+        for (int i = 0; i < BYTES / 8; ++i)
+            __builtin_nontemporal_store(*reinterpret_cast<const u32x2 *>(v.b + 8 * i),
+                                        reinterpret_cast<u32x2 *>(__builtin_assume_aligned(p, 8)) + i);
+    } else if constexpr (ALIGN >= 4 && BYTES % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < BYTES / 4; ++i)
+            __builtin_nontemporal_store(*reinterpret_cast<const uint32_t *>(v.b + 4 * i),
+                                        reinterpret_cast<uint32_t *>(__builtin_assume_aligned(p, 4)) + i);
+    } else {
+        store_raw<BYTES, ALIGN>(p, v);
+    }
+}
+
 constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
 constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Encode N pixels into a byte buffer (uint8 pixels four to a dword).
+template <typename T, int C, int N, int BYTES, int ALIGN>
+__device__ __forceinline__ void encode_run(const float (&v)[N][C], RawBuf<BYTES, ALIGN> &out)
+{
+    if constexpr (std::is_same<T, uint8_t>::value && C == 1 && N % 4 == 0) {
+#pragma unroll
+        for (int g = 0; g < N / 4; ++g) {
+            uint32_t r = u8_insert(v[4 * g][0], 0, 0u);
+            r = u8_insert(v[4 * g + 1][0], 1, r);
+            r = u8_insert(v[4 * g + 2][0], 2, r);
+            r = u8_insert(v[4 * g + 3][0], 3, r);
+            *reinterpret_cast<uint32_t *>(out.b + 4 * g) = r;
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < N; ++c)
+            Pix<T, C>::store(out.b, c, v[c]);
+    }
+}
+
 
 // ---------------------------------------------------------------------------
 // k_gather
@@ -212,6 +262,9 @@ struct StripBody {
         const unsigned char *src = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
         unsigned char *dst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
         const int32_t ncols = min(PPX, a.out_w - col0);
+        // the whole run of PPX pixels is inside the row and aligned for one
+        // vector store (PPX * PB bytes at a multiple of that size)
+        const bool full_run = ncols == PPX && a.aligned16;
 
         int32_t y = a.dst_row0 + r_begin;  // next output row to emit (logical)
         const int32_t y_end = a.dst_row0 + r_end;
@@ -230,15 +283,23 @@ struct StripBody {
             constexpr int I = decltype(slot_tag)::value;
             while (y < y_end && last == rho) {
                 unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
+                float v[PPX][C];
 #pragma unroll
                 for (int c = 0; c < PPX; ++c) {
-                    float v[C];
-                    fma_first(v, wy[0], ring[(I + 1) % K][c]);
+                    fma_first(v[c], wy[0], ring[(I + 1) % K][c]);
 #pragma unroll
                     for (int j = 1; j < K; ++j)
-                        fma_next(v, wy[j], ring[(I + 1 + j) % K][c]);
-                    if (c < ncols)
-                        Pix<T, C>::store(drow, col0 + c, v);
+                        fma_next(v[c], wy[j], ring[(I + 1 + j) % K][c]);
+                }
+                if (full_run) {
+                    RawBuf<PPX * PB, cmin(16, PPX * PB)> out;
+                    encode_run<T, C, PPX>(v, out);
+                    store_stream<PPX * PB, cmin(16, PPX * PB)>(drow + static_cast<int64_t>(col0) * PB, out);
+                } else {
+#pragma unroll
+                    for (int c = 0; c < PPX; ++c)
+                        if (c < ncols)
+                            Pix<T, C>::store(drow, col0 + c, v[c]);
                 }
                 ++y;
                 if (y < y_end) {
@@ -407,6 +468,7 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
     const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
     unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
     const int32_t ncols = min(PPX, a.out_w - col0);
+    const bool full_run = ncols == PPX && a.aligned16;
 
     int32_t y = a.dst_row0 + r_begin;  // next output row to emit (logical)
     const int32_t y_end = a.dst_row0 + r_end;
@@ -458,15 +520,23 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
         constexpr int I = decltype(slot_tag)::value;
         while (y < y_end && last == rho) {
             unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
+            float v[PPX][C];
 #pragma unroll
             for (int c = 0; c < PPX; ++c) {
-                float v[C];
-                fma_first(v, wy[0], ring[(I + 1) % K][c]);
+                fma_first(v[c], wy[0], ring[(I + 1) % K][c]);
 #pragma unroll
                 for (int j = 1; j < K; ++j)
-                    fma_next(v, wy[j], ring[(I + 1 + j) % K][c]);
-                if (c < ncols)
-                    Pix<T, C>::store(drow, col0 + c, v);
+                    fma_next(v[c], wy[j], ring[(I + 1 + j) % K][c]);
+            }
+            if (full_run) {
+                RawBuf<PPX * PB, cmin(16, PPX * PB)> out;
+                encode_run<T, C, PPX>(v, out);
+                store_stream<PPX * PB, cmin(16, PPX * PB)>(drow + static_cast<int64_t>(col0) * PB, out);
+            } else {
+#pragma unroll
+                for (int c = 0; c < PPX; ++c)
+                    if (c < ncols)
+                        Pix<T, C>::store(drow, col0 + c, v[c]);
             }
             ++y;
             if (y < y_end) {
@@ -505,26 +575,6 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
 // ---------------------------------------------------------------------------
 // k_strip_up2 (exact x2 upscale on both axes)
 // ---------------------------------------------------------------------------
-
-// Encode N pixels into a byte buffer (uint8 pixels four to a dword).
-template <typename T, int C, int N, int BYTES, int ALIGN>
-__device__ __forceinline__ void encode_run(const float (&v)[N][C], RawBuf<BYTES, ALIGN> &out)
-{
-    if constexpr (std::is_same<T, uint8_t>::value && C == 1 && N % 4 == 0) {
-#pragma unroll
-        for (int g = 0; g < N / 4; ++g) {
-            uint32_t r = u8_insert(v[4 * g][0], 0, 0u);
-            r = u8_insert(v[4 * g + 1][0], 1, r);
-            r = u8_insert(v[4 * g + 2][0], 2, r);
-            r = u8_insert(v[4 * g + 3][0], 3, r);
-            *reinterpret_cast<uint32_t *>(out.b + 4 * g) = r;
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < N; ++c)
-            Pix<T, C>::store(out.b, c, v[c]);
-    }
-}
 
 // One thread's walk down its strip. WIDE: the thread's source run and output
 // run lie inside the image and the buffers are 16-byte aligned, so rows move
@@ -620,7 +670,7 @@ struct Up2Walk {
         if constexpr (WIDE) {
             RawBuf<PPX * PB, OUT_ALIGN> out;
             encode_run<T, C, PPX>(v, out);
-            store_raw<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
+            store_stream<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
         } else {
             const int32_t ncols = min(PPX, a.out_w - col0);
 #pragma unroll
@@ -796,7 +846,7 @@ struct Down2Walk {
         if constexpr (WIDE) {
             RawBuf<PPX * PB, OUT_ALIGN> out;
             encode_run<T, C, PPX>(v, out);
-            store_raw<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
+            store_stream<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
         } else {
             const int32_t ncols = min(PPX, a.out_w - col0);
 #pragma unroll
