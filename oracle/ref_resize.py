@@ -121,6 +121,75 @@ def axis_taps(n_in: int, n_out: int, filt: int, a: float = KEYS_A, mapping: int 
     return idx, w, x0, t
 
 
+BILINEAR_AA = 3
+BICUBIC_AA = 4
+AA_RADIUS = {BILINEAR_AA: 1, BICUBIC_AA: 2}
+
+
+def axis_taps_antialiased(n_in: int, n_out: int, filt: int, a: float = KEYS_A):
+    """Antialiased taps (not in the paper; the usual remedy for aliasing when
+    shrinking): the filter is stretched by sigma = max(1, n_in / n_out), so
+    output x (pixel-centre s(x)) reads every source pixel i with
+    |i - s| < R sigma (R = 1 bilinear, 2 Keys), weight K((i - s) / sigma);
+    taps outside the image are dropped (not clamped) and the weights are
+    divided by their sum. The tap range comes from exact integers:
+    i > s - R sigma and i <= s + R sigma.
+
+    Returns (idx, w) of shape (n_out, kmax), unused slots with weight 0.
+    """
+    n_in, n_out = int(n_in), int(n_out)
+    r = AA_RADIUS[filt]
+    down = n_in > n_out
+    rows_idx, rows_w = [], []
+    for x in range(n_out):
+        num = (2 * x + 1) * n_in - n_out  # s = num / (2 n_out)
+        if down:  # sigma = n_in / n_out: s -/+ R sigma = (num -/+ 2 R n_in) / (2 n_out)
+            lo = (num - 2 * r * n_in) // (2 * n_out) + 1
+            hi = (num + 2 * r * n_in) // (2 * n_out)
+        else:     # sigma = 1
+            lo = (num - 2 * r * n_out) // (2 * n_out) + 1
+            hi = (num + 2 * r * n_out) // (2 * n_out)
+        lo, hi = max(lo, 0), min(hi, n_in - 1)
+        i = np.arange(lo, hi + 1, dtype=np.int64)
+        s = num / (2.0 * n_out)
+        sigma = n_in / n_out if down else 1.0
+        d = (i - s) / sigma
+        k = np.maximum(1.0 - np.abs(d), 0.0) if filt == BILINEAR_AA else keys_kernel(d, a)
+        rows_idx.append(i)
+        rows_w.append(k / k.sum())
+    kmax = max(len(i) for i in rows_idx)
+    idx = np.zeros((n_out, kmax), dtype=np.int64)
+    w = np.zeros((n_out, kmax))
+    for x in range(n_out):
+        idx[x, :len(rows_idx[x])] = rows_idx[x]
+        w[x, :len(rows_w[x])] = rows_w[x]
+    return idx, w
+
+
+def resize_antialiased(img, out_h: int, out_w: int, filt: int, rows=None, a: float = KEYS_A,
+                       absolute: bool = False) -> np.ndarray:
+    """Antialiased resize (BILINEAR_AA or BICUBIC_AA), pixel centres, float64,
+    shape (P, len(rows), out_w, C): the same double sum as ``resize_rows``
+    with the taps of ``axis_taps_antialiased``."""
+    src = _as_planes(img)
+    if absolute:
+        src = np.abs(src)
+    _, in_h, in_w, _ = src.shape
+    rows = np.arange(out_h) if rows is None else np.asarray(rows, dtype=np.int64)
+    iy, wy = axis_taps_antialiased(in_h, out_h, filt, a)
+    ix, wx = axis_taps_antialiased(in_w, out_w, filt, a)
+    iy, wy = iy[rows], wy[rows]
+    if absolute:
+        wy, wx = np.abs(wy), np.abs(wx)
+    out = np.zeros((src.shape[0], rows.size, out_w, src.shape[3]), dtype=np.float64)
+    for j in range(iy.shape[1]):
+        src_rows = src[:, iy[:, j]]
+        for i in range(ix.shape[1]):
+            wgt = wy[:, j][:, None] * wx[:, i][None, :]
+            out += wgt[None, :, :, None] * src_rows[:, :, ix[:, i]]
+    return out
+
+
 def _as_planes(img) -> np.ndarray:
     img = np.asarray(img)
     if img.ndim == 2:

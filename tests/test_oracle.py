@@ -10,6 +10,9 @@
   maps) and its backward, PIL float-mode bicubic in the interior;
 * the paper's printed map (eq. 1, x_p = x_f / scale): exact brute force, the
   x2 closed form, and eqs. 1-5 evaluated literally pixel by pixel;
+* the antialiased variant: PIL float-mode resize on whole images (edges
+  renormalised alike), the x0.5 bilinear closed form, the plain filters in the
+  interior when growing, partition of unity;
 * adjoint by finite differences, by <Ax, y> = <x, A^T y> and by mass conservation;
 * a mutation check: plausible mistakes planted into a copy of the oracle must
   be caught by the brute-force pin.
@@ -399,6 +402,61 @@ def test_pil_bicubic_interior():
         assert m.sum() > 0
         # PIL keeps its intermediate rows in float32
         np.testing.assert_allclose(got[m], want[m], rtol=0, atol=2e-4)
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR_AA, R.BICUBIC_AA])
+@pytest.mark.parametrize("sizes", [(64, 64, 32, 32), (50, 37, 13, 20), (40, 90, 17, 11), (33, 33, 33, 33),
+                                   (16, 12, 40, 30), (9, 300, 5, 19)])
+def test_pil_antialiased_pin(filt, sizes):
+    """PIL's float-mode resize stretches its filters by the shrink factor and
+    renormalises the taps it keeps at the edges: the whole image, edges
+    included, must match (PIL keeps its intermediate rows in float32)."""
+    Image = pytest.importorskip("PIL.Image")
+    in_h, in_w, out_h, out_w = sizes
+    img = fields.field_u8(in_h, in_w, 1, seed=in_h + in_w)[:, :, 0].astype(np.float32)
+    pil_filter = Image.BILINEAR if filt == R.BILINEAR_AA else Image.BICUBIC
+    want = np.asarray(Image.fromarray(img, mode="F").resize((out_w, out_h), resample=pil_filter),
+                      dtype=np.float64)
+    got = R.resize_antialiased(img, out_h, out_w, filt)[0, :, :, 0]
+    np.testing.assert_allclose(got, want, rtol=0, atol=3e-4)
+
+
+def test_antialiased_closed_form_bilinear_half():
+    """x0.5 bilinear, antialiased: s = 2x + 1/2, sigma = 2, taps 2x-1 .. 2x+2
+    at distances (-3/4, -1/4, 1/4, 3/4), weights (1, 3, 3, 1) / 8."""
+    idx, w = R.axis_taps_antialiased(16, 8, R.BILINEAR_AA)
+    for x in range(1, 7):
+        assert idx[x].tolist() == [2 * x - 1, 2 * x, 2 * x + 1, 2 * x + 2]
+        np.testing.assert_allclose(w[x], np.array([1, 3, 3, 1]) / 8, rtol=0, atol=1e-15)
+    # at the left edge tap -1 is dropped and the rest renormalised: (3, 3, 1) / 7
+    assert idx[0].tolist()[:3] == [0, 1, 2]
+    np.testing.assert_allclose(w[0][:3], np.array([3, 3, 1]) / 7, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("filt, plain", [(R.BILINEAR_AA, R.BILINEAR), (R.BICUBIC_AA, R.BICUBIC)])
+def test_antialiased_upscale_interior_is_plain(filt, plain):
+    """sigma = 1 when growing: away from the edges every tap is inside the
+    image, the weights already sum to one, and the plain filter results."""
+    img = fields.uniform_u8((21, 17), seed=5).astype(np.float64)
+    got = R.resize_antialiased(img, 50, 41, filt)[0, :, :, 0]
+    want = R.resize(img, 50, 41, plain)[0, :, :, 0]
+    sy, my = _interior(21, 50, 1, 1)
+    sx, mx = _interior(17, 41, 1, 1)
+    r = 2 if plain == R.BICUBIC else 1
+    my &= (np.floor(sy) - (r - 1) >= 0) & (np.floor(sy) + r <= 20)
+    mx &= (np.floor(sx) - (r - 1) >= 0) & (np.floor(sx) + r <= 16)
+    m = my[:, None] & mx[None, :]
+    assert m.sum() > 0
+    np.testing.assert_allclose(got[m], want[m], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR_AA, R.BICUBIC_AA])
+def test_antialiased_constant_and_sum(filt):
+    for n_in, n_out in [(100, 7), (37, 29), (5, 9), (64, 1)]:
+        _, w = R.axis_taps_antialiased(n_in, n_out, filt)
+        np.testing.assert_allclose(w.sum(axis=1), 1.0, rtol=0, atol=1e-14)
+    img = np.full((30, 40), 77.0)
+    np.testing.assert_allclose(R.resize_antialiased(img, 7, 9, filt), 77.0, rtol=0, atol=1e-12)
 
 
 # ---------------------------------------------------------------------------
