@@ -355,6 +355,8 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         for direction, n in [("x2", 8192), ("x0.5", 2048)]:
             measure(f"c2_bicubic_{direction}_{dname}_rgba", lambda t=t: t, (n, n, 4), "bicubic")
     measure("nearest_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "nearest")
+    measure("bicubic_aa_x0.5_u8_rgba", lambda: u8, (2048, 2048, 4), "bicubic_aa")
+    measure("bilinear_aa_x0.25_u8_rgba", lambda: u8, (1024, 1024, 4), "bilinear_aa")
     measure("bilinear_paper_map_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "bilinear", mapping="paper")
     measure("bicubic_paper_map_x3_u8_rgba", lambda: u8, (12288, 12288, 4), "bicubic", mapping="paper")
     del fld, unit, u8

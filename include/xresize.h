@@ -63,6 +63,8 @@ extern "C" {
 #define XR_BILINEAR 0
 #define XR_BICUBIC 1
 #define XR_NEAREST 2        /* xr_resize only */
+#define XR_BILINEAR_AA 3    /* xr_resize only: antialiased (filter stretched when shrinking) */
+#define XR_BICUBIC_AA 4     /* xr_resize only: antialiased Keys a = -1/2 */
 
 /* coordinate maps of xr_resize (eq. 1) */
 #define XR_MAP_HALF_PIXEL 0 /* s = ((2x + 1) N_in - N_out) / (2 N_out): pixel centres aligned */
@@ -163,6 +165,15 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
  *            floor(s) under XR_MAP_PAPER (pixel i covers [i, i + 1)); it
  *            copies source values exactly. Nearest neighbour is one of the
  *            interpolation methods section II of the paper names.
+ *          XR_BILINEAR_AA / XR_BICUBIC_AA (not in the paper; PIL's
+ *            convention): the filter stretched by sigma = max(1, N_in/N_out),
+ *            taps |i - s| < R sigma (R = 1, 2) inside the image (dropped, not
+ *            clamped, at the edges), weights K((i - s)/sigma) divided by their
+ *            sum (float32). Pixel-centre map only. Always one pixel per thread
+ *            in a block of the tile's block_w x block_h (a gather tile; other
+ *            kinds use 64 x 4); XR_ERR_ARG when the workgroup's weight tables,
+ *            4 (2 bw + 2 bh + bw kx + bh ky) bytes with k = floor(2 R sigma) + 1,
+ *            exceed 64 KiB.
  *  mapping = XR_MAP_HALF_PIXEL (as xr_resize_bilinear / _bicubic) or
  *            XR_MAP_PAPER: s = x N_in / N_out, the map of eq. 1 as printed
  *            (x_p = x_f / scale with scale = N_out / N_in from the sizes);

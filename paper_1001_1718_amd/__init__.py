@@ -28,6 +28,8 @@ from ._lib import (  # noqa: F401
     XR_MAP_HALF_PIXEL,
     XR_MAP_PAPER,
     XR_NEAREST,
+    XR_BILINEAR_AA,
+    XR_BICUBIC_AA,
     XR_U8,
     XResizeError,
     XrImage,
@@ -39,7 +41,8 @@ from ._lib import (  # noqa: F401
 )
 
 _DTYPES = {torch.uint8: XR_U8, torch.float16: XR_F16, torch.float32: XR_F32}
-_FILTERS = {"bilinear": XR_BILINEAR, "bicubic": XR_BICUBIC, "nearest": XR_NEAREST}
+_FILTERS = {"bilinear": XR_BILINEAR, "bicubic": XR_BICUBIC, "nearest": XR_NEAREST,
+            "bilinear_aa": XR_BILINEAR_AA, "bicubic_aa": XR_BICUBIC_AA}
 _MAPPINGS = {"half_pixel": XR_MAP_HALF_PIXEL, "paper": XR_MAP_PAPER}
 
 
@@ -49,7 +52,7 @@ def filter_code(mode) -> int:
     try:
         return _FILTERS[mode]
     except KeyError:
-        raise ValueError(f"mode must be 'bilinear', 'bicubic' or 'nearest', not {mode!r}") from None
+        raise ValueError(f"mode must be one of {sorted(_FILTERS)}, not {mode!r}") from None
 
 
 def mapping_code(mapping) -> int:
@@ -122,12 +125,13 @@ def resize_into(src: torch.Tensor, dst: torch.Tensor, mode="bilinear", layout="h
                 src_row0: int = 0, src_height: int | None = None, dst_row0: int = 0,
                 dst_height: int | None = None, stream=None, mapping="half_pixel") -> torch.Tensor:
     """Resize ``src`` into the preallocated ``dst`` (both on the same GPU).
-    ``mode``: 'bilinear', 'bicubic' or 'nearest'; ``mapping``: 'half_pixel'
-    (pixel centres) or 'paper' (eq. 1 as printed, s = x * in / out)."""
+    ``mode``: 'bilinear', 'bicubic', 'nearest', 'bilinear_aa' or 'bicubic_aa'
+    (antialiased: the filter stretched when shrinking); ``mapping``:
+    'half_pixel' (pixel centres) or 'paper' (eq. 1 as printed, s = x * in / out)."""
     s = image(src, layout, src_row0, src_height)
     d = image(dst, layout, dst_row0, dst_height)
     f, m = filter_code(mode), mapping_code(mapping)
-    if m == XR_MAP_HALF_PIXEL and f != XR_NEAREST:
+    if m == XR_MAP_HALF_PIXEL and f in (XR_BILINEAR, XR_BICUBIC):
         fn = lib.xr_resize_bicubic if f == XR_BICUBIC else lib.xr_resize_bilinear
         rc = fn(ctypes.byref(s), ctypes.byref(d), _tile_ptr(tile), _stream_handle(src, stream))
     else:

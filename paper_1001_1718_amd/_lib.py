@@ -27,7 +27,7 @@ XR_ERR_HIP = 10
 XR_ERR_ARG = 11
 
 XR_U8, XR_F16, XR_F32 = 0, 1, 2
-XR_BILINEAR, XR_BICUBIC, XR_NEAREST = 0, 1, 2
+XR_BILINEAR, XR_BICUBIC, XR_NEAREST, XR_BILINEAR_AA, XR_BICUBIC_AA = 0, 1, 2, 3, 4
 XR_MAP_HALF_PIXEL, XR_MAP_PAPER = 0, 1
 XR_MAX_SIDE = 32768
 XR_KERNEL_AUTO, XR_KERNEL_GATHER, XR_KERNEL_STRIP, XR_KERNEL_STRIP_ANY, XR_KERNEL_STRIP_LDS = 0, 1, 2, 3, 4

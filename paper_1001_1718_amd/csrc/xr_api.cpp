@@ -63,8 +63,15 @@ int64_t floor_div(int64_t a, int64_t b)
 
 bool valid_filter(int32_t filter)
 {
-    return filter == XR_BILINEAR || filter == XR_BICUBIC || filter == XR_NEAREST;
+    return filter == XR_BILINEAR || filter == XR_BICUBIC || filter == XR_NEAREST ||
+           filter == XR_BILINEAR_AA || filter == XR_BICUBIC_AA;
 }
+bool is_aa(int32_t filter) { return filter == XR_BILINEAR_AA || filter == XR_BICUBIC_AA; }
+int32_t aa_radius(int32_t filter) { return filter == XR_BICUBIC_AA ? 2 : 1; }
+
+// Antialiased taps of output index x (radius r): every i with
+// s - r sigma < i <= s + r sigma inside [0, n_in - 1], sigma = max(1, n_in/n_out).
+void aa_taps(int64_t x, int64_t n_in, int64_t n_out, int32_t r, int64_t *lo, int64_t *hi);
 bool valid_mapping(int32_t mapping) { return mapping == XR_MAP_HALF_PIXEL || mapping == XR_MAP_PAPER; }
 
 // Base tap of output index x (eqs. 1-4) with o = 1 for pixel centres,
@@ -83,9 +90,25 @@ int64_t base_tap(int64_t x, int64_t n_in, int64_t n_out, int32_t filter = XR_BIL
 int taps_of(int32_t filter) { return filter == XR_BICUBIC ? 4 : (filter == XR_NEAREST ? 1 : 2); }
 int first_offset(int32_t filter) { return filter == XR_BICUBIC ? -1 : 0; }
 
+void aa_taps(int64_t x, int64_t n_in, int64_t n_out, int32_t r, int64_t *lo, int64_t *hi)
+{
+    const int64_t num = (2 * x + 1) * n_in - n_out;
+    const int64_t reach = 2 * r * std::max(n_in, n_out);
+    *lo = std::max<int64_t>(floor_div(num - reach, 2 * n_out) + 1, 0);
+    *hi = std::min<int64_t>(floor_div(num + reach, 2 * n_out), n_in - 1);
+}
+
 void needed_rows(int32_t in_h, int32_t out_h, int32_t row0, int32_t rows, int32_t filter,
                  int32_t *first, int32_t *last, int32_t mapping = XR_MAP_HALF_PIXEL)
 {
+    if (is_aa(filter)) {
+        int64_t lo, hi, lo2, hi2;
+        aa_taps(row0, in_h, out_h, aa_radius(filter), &lo, &hi);
+        aa_taps(row0 + rows - 1, in_h, out_h, aa_radius(filter), &lo2, &hi2);
+        *first = static_cast<int32_t>(lo);
+        *last = static_cast<int32_t>(hi2);
+        return;
+    }
     const int64_t lo = base_tap(row0, in_h, out_h, filter, mapping) + first_offset(filter);
     const int64_t hi = base_tap(row0 + rows - 1, in_h, out_h, filter, mapping) + first_offset(filter) +
                        taps_of(filter) - 1;
@@ -153,9 +176,11 @@ int check_pair(const xr_image *src, const xr_image *dst, int32_t filter,
                int32_t mapping = XR_MAP_HALF_PIXEL)
 {
     if (!valid_filter(filter))
-        return fail(XR_ERR_ARG, "filter = %d is not XR_BILINEAR, XR_BICUBIC or XR_NEAREST", filter);
+        return fail(XR_ERR_ARG, "filter = %d is not one of XR_BILINEAR .. XR_BICUBIC_AA", filter);
     if (!valid_mapping(mapping))
         return fail(XR_ERR_ARG, "mapping = %d is not XR_MAP_HALF_PIXEL or XR_MAP_PAPER", mapping);
+    if (is_aa(filter) && mapping != XR_MAP_HALF_PIXEL)
+        return fail(XR_ERR_ARG, "the antialiased filters take the pixel-centre map");
     int rc = check_image(src, "src");
     if (rc)
         return rc;
@@ -220,7 +245,8 @@ xr::ResizeArgs make_args(const xr_image &src, const xr_image &dst, int32_t mappi
 int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t, int32_t filter,
                   int32_t mapping)
 {
-    if (t.kernel != XR_KERNEL_STRIP || mapping != XR_MAP_HALF_PIXEL || filter == XR_NEAREST)
+    if (t.kernel != XR_KERNEL_STRIP || mapping != XR_MAP_HALF_PIXEL || filter == XR_NEAREST ||
+        is_aa(filter))
         return xr::kGeneral;
     if (dst.width == 2 * src.width && dst.height == 2 * src.height)
         return xr::kUp2;
@@ -368,6 +394,20 @@ int check_lds(const xr_tile &t, int32_t filter, int32_t dtype, int32_t channels,
     return XR_OK;
 }
 
+int check_aa(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
+{
+    if (!is_aa(filter))
+        return XR_OK;
+    const xr::AaPlan p = xr::aa_plan(src.width, src.height, dst.width, dst.height, aa_radius(filter),
+                                     t.block_w, t.block_h);
+    if (p.lds_bytes > xr::kAaLdsBudget)
+        return fail(XR_ERR_ARG,
+                    "antialiased resize: weight tables of a %dx%d block (%d x %d taps) need %lld bytes "
+                    "of LDS (limit %lld); use a smaller block", t.block_w, t.block_h, p.kx, p.ky,
+                    static_cast<long long>(p.lds_bytes), static_cast<long long>(xr::kAaLdsBudget));
+    return XR_OK;
+}
+
 bool lds_usable(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
 {
     return xr::strip_lds_fits(filter, src.dtype, src.channels, src.width, dst.width, t.block_w,
@@ -407,8 +447,13 @@ int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile,
     int rc = check_pair(src, dst, filter, mapping);
     if (rc)
         return rc;
-    const xr_tile t = resolve_tile(tile, filter, *src, *dst);
+    xr_tile t = resolve_tile(tile, filter, *src, *dst);
+    if (is_aa(filter) && t.kernel != XR_KERNEL_GATHER)
+        t = xr_tile{XR_KERNEL_GATHER, 64, 4, 1, 1, 0};  // the antialiased kernel is a gather
     rc = check_tile(t, src->dtype, src->channels);
+    if (rc)
+        return rc;
+    rc = check_aa(t, filter, *src, *dst);
     if (rc)
         return rc;
     rc = check_grid(t, *dst);
@@ -507,7 +552,7 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
         const int rc = check_pair(&jobs[k].src, &jobs[k].dst, jobs[k].filter);
         if (rc)
             return fail(rc, "job %d: %s", k, g_last_error.c_str());
-        if (jobs[k].filter == XR_NEAREST)
+        if (jobs[k].filter != XR_BILINEAR && jobs[k].filter != XR_BICUBIC)
             return fail(XR_ERR_ARG, "job %d: the batched launch takes XR_BILINEAR or XR_BICUBIC", k);
         if (jobs[k].src.dtype != dtype)
             return fail(XR_ERR_DTYPE, "job %d: dtype %d differs from job 0 (%d)", k, jobs[k].src.dtype,
@@ -753,6 +798,12 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
                              {128, 2}, {256, 1}};
     for (const auto &g : gather)
         c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1, 0});
+    if (is_aa(filter)) {  // the antialiased kernel is a gather: block shapes only
+        if (out)
+            for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)
+                out[k] = c[k];
+        return static_cast<int32_t>(c.size());
+    }
     const int ppx_c4[3] = {2, 4, 8};
     const int ppx_c1[3] = {4, 8, 16};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
@@ -817,11 +868,17 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         cand.resize(n);
         xr_tune_candidates(filter, src->dtype, src->channels, src->width, src->height, dst->width,
                            dst->height, cand.data(), n);
-        // the built-in list assumes aligned sources; drop the LDS shapes
-        // these sources cannot use
+        // the built-in list assumes aligned sources and narrow weight tables;
+        // drop the shapes these sources cannot use
         for (int32_t k = 0; k < n_pairs; ++k)
             cand.erase(std::remove_if(cand.begin(), cand.end(),
                                       [&](const xr_tile &t) {
+                                          if (is_aa(filter))
+                                              return xr::aa_plan(srcs[k].width, srcs[k].height,
+                                                                 dsts[k].width, dsts[k].height,
+                                                                 aa_radius(filter), t.block_w,
+                                                                 t.block_h)
+                                                         .lds_bytes > xr::kAaLdsBudget;
                                           return t.kernel == XR_KERNEL_STRIP_LDS &&
                                                  !lds_usable(t, filter, srcs[k], dsts[k]);
                                       }),
@@ -836,6 +893,10 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         if (!rc)
             rc = check_lds(cand[k], filter, src->dtype, src->channels, src->width, dst->width,
                            std::all_of(srcs, srcs + n_pairs, [](const xr_image &i) { return src_aligned4(i); }));
+        if (!rc && is_aa(filter) && cand[k].kernel != XR_KERNEL_GATHER)
+            rc = fail(XR_ERR_ARG, "the antialiased filters take gather tiles");
+        if (!rc)
+            rc = check_aa(cand[k], filter, *src, *dst);
         if (rc)
             return fail(rc, "candidate %zu: %s", k, g_last_error.c_str());
     }

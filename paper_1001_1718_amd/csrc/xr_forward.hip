@@ -171,6 +171,132 @@ __global__ void __launch_bounds__(1024) k_gather(ResizeArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// k_gather_aa (antialiased: filter stretched by the shrink factor)
+// ---------------------------------------------------------------------------
+
+// Taps of output index x for an antialiased filter of radius R (1 bilinear,
+// 2 Keys): sigma = max(1, n_in / n_out), every source i with
+// s - R sigma < i <= s + R sigma inside [0, n_in - 1], from exact integers
+// (s = num / (2 n_out), num = (2x + 1) n_in - n_out). Not in the paper: the
+// usual remedy for aliasing when shrinking.
+__device__ __forceinline__ void aa_range(int32_t x, int32_t n_in, int32_t n_out, int32_t r,
+                                         int32_t &lo, int32_t &hi)
+{
+    const int64_t num = (2 * static_cast<int64_t>(x) + 1) * n_in - n_out;
+    const int64_t den = 2 * static_cast<int64_t>(n_out);
+    const int64_t reach = 2 * static_cast<int64_t>(r) * (n_in > n_out ? n_in : n_out);
+    // floor division of possibly negative numerators
+    auto fdiv = [](int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); };
+    lo = static_cast<int32_t>(max<int64_t>(fdiv(num - reach, den) + 1, 0));
+    hi = static_cast<int32_t>(min<int64_t>(fdiv(num + reach, den), n_in - 1));
+}
+
+// K(d) in factored forms whose factors do not cancel: 1 - u; Keys a = -1/2
+// as (1 - u)(1 + u (1 - 3u/2)) for u <= 1 and -(u - 1)(u - 2)^2 / 2 for
+// 1 < u < 2 (u - 1 and u - 2 are exact there).
+template <int R>
+__device__ __forceinline__ float aa_kernel(float d)
+{
+    const float u = fabsf(d);
+    if constexpr (R == 1) {
+        return u < 1.0f ? 1.0f - u : 0.0f;
+    } else {
+        if (u <= 1.0f)
+            return (1.0f - u) * (1.0f + u * (1.0f - 1.5f * u));
+        if (u < 2.0f) {
+            const float v = u - 2.0f;
+            return (-0.5f * (u - 1.0f)) * (v * v);
+        }
+        return 0.0f;
+    }
+}
+
+// Taps and normalised weights of one output index into an LDS table: the
+// kernel values K((i - s) / sigma) for i = lo .. hi, then each divided by
+// their sum (summed in ascending i).
+template <int R>
+__device__ __forceinline__ void aa_table(int32_t x, int32_t n_in, int32_t n_out, int32_t kmax,
+                                         int32_t *lo_out, int32_t *n_out_taps, float *w)
+{
+    int32_t lo, hi;
+    aa_range(x, n_in, n_out, R, lo, hi);
+    const int32_t n = min(hi - lo + 1, kmax);
+    // (i - s) / sigma = (2 i n_out - num) / (2 max(n_in, n_out)) from exact
+    // integers: one rounding, no cancellation
+    const int64_t num = (2 * static_cast<int64_t>(x) + 1) * n_in - n_out;
+    const float den = static_cast<float>(2 * static_cast<int64_t>(n_in > n_out ? n_in : n_out));
+    float sum = 0.0f;
+    for (int32_t k = 0; k < n; ++k) {
+        const int64_t dn = 2 * static_cast<int64_t>(lo + k) * n_out - num;
+        const float v = aa_kernel<R>(static_cast<float>(dn) / den);
+        w[k] = v;
+        sum += v;
+    }
+    const float inv = 1.0f / sum;
+    for (int32_t k = 0; k < n; ++k)
+        w[k] *= inv;
+    *lo_out = lo;
+    *n_out_taps = n;
+}
+
+// One output pixel per thread in a block_w x block_h tile (the paper's
+// tiling, eq. 6). The workgroup first fills LDS tables of taps and weights
+// for its block_w columns and block_h rows (kx / ky weights each), then every
+// thread sums its window: per source row the taps ascending (multiply, then
+// FMAs), then the rows ascending.
+template <int R, typename T, int C>
+__global__ void __launch_bounds__(1024) k_gather_aa(ResizeArgs a, int32_t kx, int32_t ky)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int32_t bw = static_cast<int32_t>(blockDim.x), bh = static_cast<int32_t>(blockDim.y);
+    int32_t *xlo = reinterpret_cast<int32_t *>(lds);
+    int32_t *xn = xlo + bw;
+    int32_t *ylo = xn + bw;
+    int32_t *yn = ylo + bh;
+    float *xw = reinterpret_cast<float *>(yn + bh);
+    float *yw = xw + bw * kx;
+    const int32_t tid = threadIdx.y * bw + threadIdx.x;
+    for (int32_t t = tid; t < bw + bh; t += bw * bh) {
+        if (t < bw) {
+            const int32_t x = min(static_cast<int32_t>(blockIdx.x) * bw + t, a.out_w - 1);
+            aa_table<R>(x, a.in_w, a.out_w, kx, xlo + t, xn + t, xw + t * kx);
+        } else {
+            const int32_t u = t - bw;
+            const int32_t y = a.dst_row0 + min(static_cast<int32_t>(blockIdx.y) * bh + u, a.dst_rows - 1);
+            aa_table<R>(y, a.in_h, a.out_h, ky, ylo + u, yn + u, yw + u * ky);
+        }
+    }
+    __syncthreads();
+    const int32_t px = blockIdx.x * bw + threadIdx.x;
+    const int32_t py = blockIdx.y * bh + threadIdx.y;
+    if (px >= a.out_w || py >= a.dst_rows)
+        return;
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
+    const int32_t x0 = xlo[threadIdx.x], nx = xn[threadIdx.x];
+    const int32_t y0 = ylo[threadIdx.y], ny = yn[threadIdx.y];
+    const float *wxr = xw + threadIdx.x * kx;
+    const float *wyr = yw + threadIdx.y * ky;
+    float acc[C];
+    for (int32_t j = 0; j < ny; ++j) {
+        const unsigned char *row = src + static_cast<int64_t>(y0 + j - a.src_row0) * a.src_pitch;
+        float h[C], p[C];
+        Pix<T, C>::load(row, x0, p);
+        fma_first(h, wxr[0], p);
+        for (int32_t i = 1; i < nx; ++i) {
+            Pix<T, C>::load(row, x0 + i, p);
+            fma_next(h, wxr[i], p);
+        }
+        if (j == 0)
+            fma_first(acc, wyr[0], h);
+        else
+            fma_next(acc, wyr[j], h);
+    }
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                         static_cast<int64_t>(py) * a.dst_pitch;
+    Pix<T, C>::store(dst, px, acc);
+}
+
+// ---------------------------------------------------------------------------
 // k_strip (any scale)
 // ---------------------------------------------------------------------------
 
@@ -1200,9 +1326,45 @@ hipError_t launch_filter(const ResizeArgs &a, int32_t dtype, int32_t channels, c
 
 }  // namespace
 
+namespace {
+template <int R, typename T, int C>
+hipError_t launch_aa_typed(const ResizeArgs &a, const xr_tile &tile, hipStream_t stream)
+{
+    const AaPlan plan = aa_plan(a.in_w, a.in_h, a.out_w, a.out_h, R, tile.block_w, tile.block_h);
+    const dim3 block(tile.block_w, tile.block_h, 1);
+    const dim3 grid((a.out_w + tile.block_w - 1) / tile.block_w,
+                    (a.dst_rows + tile.block_h - 1) / tile.block_h, a.planes);
+    hipLaunchKernelGGL((k_gather_aa<R, T, C>), grid, block, plan.lds_bytes, stream, a, plan.kx, plan.ky);
+    return hipGetLastError();
+}
+
+template <int R>
+hipError_t launch_aa(const ResizeArgs &a, int32_t dtype, int32_t channels, const xr_tile &tile,
+                     hipStream_t stream)
+{
+    switch (dtype) {
+    case XR_U8:
+        return channels == 4 ? launch_aa_typed<R, uint8_t, 4>(a, tile, stream)
+                             : launch_aa_typed<R, uint8_t, 1>(a, tile, stream);
+    case XR_F16:
+        return channels == 4 ? launch_aa_typed<R, _Float16, 4>(a, tile, stream)
+                             : launch_aa_typed<R, _Float16, 1>(a, tile, stream);
+    case XR_F32:
+        return channels == 4 ? launch_aa_typed<R, float, 4>(a, tile, stream)
+                             : launch_aa_typed<R, float, 1>(a, tile, stream);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
 hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
                           const xr_tile &tile, int32_t mode, hipStream_t stream)
 {
+    if (filter == XR_BILINEAR_AA)
+        return launch_aa<1>(a, dtype, channels, tile, stream);
+    if (filter == XR_BICUBIC_AA)
+        return launch_aa<2>(a, dtype, channels, tile, stream);
     if (filter == XR_BICUBIC)
         return launch_filter<kBicubic>(a, dtype, channels, tile, mode, stream);
     if (filter == XR_NEAREST)

@@ -70,6 +70,28 @@ hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels
 // (vertical upscale beyond roughly 190x).
 bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels);
 
+// Weight tables of the antialiased kernel: at most kx (ky) taps per output
+// column (row), floor(2 R sigma) + 1 with sigma = max(1, n_in / n_out), and
+// the LDS bytes of one workgroup's tables.
+struct AaPlan {
+    int32_t kx, ky;
+    int64_t lds_bytes;
+};
+inline AaPlan aa_plan(int32_t in_w, int32_t in_h, int32_t out_w, int32_t out_h, int32_t r,
+                      int32_t block_w, int32_t block_h)
+{
+    const auto taps = [r](int64_t n_in, int64_t n_out) {
+        return static_cast<int32_t>((n_in > n_out ? (2 * r * n_in) / n_out : 2 * r) + 1);
+    };
+    AaPlan p;
+    p.kx = taps(in_w, out_w);
+    p.ky = taps(in_h, out_h);
+    p.lds_bytes = 4 * (2 * static_cast<int64_t>(block_w) + 2 * block_h +
+                       static_cast<int64_t>(block_w) * p.kx + static_cast<int64_t>(block_h) * p.ky);
+    return p;
+}
+constexpr int64_t kAaLdsBudget = 64 * 1024;
+
 // Pixels per thread along x that the strip kernel is instantiated for.
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx);
 // Columns per thread of the LDS-staged strip kernel: {one channel, four}.

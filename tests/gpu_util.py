@@ -85,8 +85,9 @@ def compare(gpu: np.ndarray, src_np: np.ndarray, out_h: int, out_w: int, filt: i
     storage type; the C oracle covers the pixel-centre map with 2 or 4 taps."""
     from oracle import ref_c
 
-    if mapping != R.HALF_PIXEL or filt == R.NEAREST:
+    if mapping != R.HALF_PIXEL or filt not in (R.BILINEAR, R.BICUBIC):
         use_c = False
+    aa = filt in (R.BILINEAR_AA, R.BICUBIC_AA)
 
     planes = src_np if src_np.ndim == 4 else (src_np[None] if src_np.ndim == 3 else src_np[None, :, :, None])
     in_h, in_w = planes.shape[1], planes.shape[2]
@@ -97,17 +98,23 @@ def compare(gpu: np.ndarray, src_np: np.ndarray, out_h: int, out_w: int, filt: i
         gpu = gpu[None, :, :, None]
     elif gpu.ndim == 3:
         gpu = gpu[None]
-    ref = (ref_c.resize_rows(planes, out_h, out_w, rows, filt) if use_c
-           else R.resize_rows(planes, out_h, out_w, rows, filt, mapping=mapping))
+    if aa:
+        ref = R.resize_antialiased(planes, out_h, out_w, filt, rows=rows)
+    elif use_c:
+        ref = ref_c.resize_rows(planes, out_h, out_w, rows, filt)
+    else:
+        ref = R.resize_rows(planes, out_h, out_w, rows, filt, mapping=mapping)
     if filt == R.NEAREST:
         want = ref.astype(planes.dtype)
         np.testing.assert_array_equal(np.asarray(gpu).reshape(want.shape).view(np.uint8),
                                       want.view(np.uint8), err_msg=f"{what}: nearest is not an exact copy")
         return 0
     if planes.dtype == np.uint8:
-        exact = is_dyadic_ratio(in_w, out_w, mapping) and is_dyadic_ratio(in_h, out_h, mapping)
+        # antialiased weights are normalised in float32: never exact
+        exact = (not aa) and is_dyadic_ratio(in_w, out_w, mapping) and is_dyadic_ratio(in_h, out_h, mapping)
         return check_u8(gpu, ref, exact, what)
     if planes.dtype == np.float16:
         return check_f16(gpu, ref, what)
-    scale = R.resize_rows(planes, out_h, out_w, rows, filt, absolute=True, mapping=mapping)
+    scale = (R.resize_antialiased(planes, out_h, out_w, filt, rows=rows, absolute=True) if aa
+             else R.resize_rows(planes, out_h, out_w, rows, filt, absolute=True, mapping=mapping))
     return check_f32(gpu, ref, scale, what)

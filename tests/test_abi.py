@@ -176,9 +176,33 @@ def test_batch_validation():
 def test_resize_with_mapping_validates_first():
     f = _lib.lib.xr_resize
     s, d = _img(), _img(32, 32, data=D2)
-    assert f(ctypes.byref(s), ctypes.byref(d), 3, 0, None, None) == 11   # unknown filter
+    assert f(ctypes.byref(s), ctypes.byref(d), 7, 0, None, None) == 11   # unknown filter
+    assert f(ctypes.byref(s), ctypes.byref(d), 4, 1, None, None) == 11   # antialiased + printed map
     assert f(ctypes.byref(s), ctypes.byref(d), 2, 2, None, None) == 11   # unknown mapping
     assert f(None, ctypes.byref(d), 2, 1, None, None) == 1
+
+
+@pytest.mark.parametrize("filt", [3, 4])
+def test_needed_rows_antialiased_match_oracle(filt):
+    from oracle import ref_resize as R
+
+    for in_h, out_h in [(17, 40), (40, 17), (300, 71), (64, 4), (9, 9)]:
+        idx, w = R.axis_taps_antialiased(in_h, out_h, filt)
+        for row0, rows in [(0, 1), (0, out_h), (out_h // 3, max(1, out_h // 4)), (out_h - 1, 1)]:
+            sel = [idx[y][w[y] != 0] for y in range(row0, row0 + rows)]
+            first, last = ctypes.c_int32(), ctypes.c_int32()
+            assert _lib.lib.xr_needed_rows_map(in_h, out_h, row0, rows, filt, 0, ctypes.byref(first),
+                                               ctypes.byref(last)) == 0
+            # the library's range holds every tap with a nonzero weight ...
+            assert first.value <= min(int(t.min()) for t in sel)
+            assert last.value >= max(int(t.max()) for t in sel)
+            # ... and no row outside (s - R sigma, s + R sigma] of its end rows
+            r = 2 if filt == 4 else 1
+            sigma = max(1.0, in_h / out_h)
+            s0 = (row0 + 0.5) * in_h / out_h - 0.5
+            s1 = (row0 + rows - 1 + 0.5) * in_h / out_h - 0.5
+            assert first.value >= max(0, int(np.floor(s0 - r * sigma)) + 1)
+            assert last.value <= min(in_h - 1, int(np.floor(s1 + r * sigma)))
 
 
 @pytest.mark.parametrize("filt", [0, 1, 2])

@@ -21,7 +21,7 @@ from gpu_util import compare  # noqa: E402
 from synth import fields  # noqa: E402
 
 DEV = "cuda:0"
-MODES = {"bilinear": 0, "bicubic": 1, "nearest": 2}
+MODES = {"bilinear": 0, "bicubic": 1, "nearest": 2, "bilinear_aa": 3, "bicubic_aa": 4}
 R_MAP = {"half_pixel": 0, "paper": 1}
 
 TILES = {
@@ -179,6 +179,64 @@ def _gpu_map(src_np, out_h, out_w, mode, mapping):
     y = xr.resize(torch.from_numpy(src_np).to(DEV), (out_h, out_w), mode, mapping=mapping)
     torch.cuda.synchronize()
     return y.cpu().numpy()
+
+
+AA_SHAPES = [
+    ((64, 96), (32, 48)),     # x0.5
+    ((150, 70), (41, 23)),    # strong, non-dyadic shrink
+    ((37, 53), (61, 29)),     # grow rows, shrink columns
+    ((33, 21), (33, 21)),     # identity
+    ((300, 17), (19, 17)),    # ~x16 rows
+    ((5, 9), (12, 20)),       # grow: edges renormalised
+]
+AA_TILES = [None, xr.tile(xr.XR_KERNEL_GATHER, 8, 8), xr.tile(xr.XR_KERNEL_GATHER, 32, 4),
+            xr.tile(xr.XR_KERNEL_GATHER, 256, 1), xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 4, 7)]
+
+
+@pytest.mark.parametrize("shape", AA_SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
+@pytest.mark.parametrize("dtype", [np.uint8, np.float16, np.float32], ids=["u8", "f16", "f32"])
+@pytest.mark.parametrize("channels", [1, 4])
+@pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
+def test_antialiased(shape, dtype, channels, mode):
+    """The antialiased kernel: every block shape bitwise equal (a strip tile
+    runs the same gather), within the storage rule of the FP64 antialiased
+    oracle (float32 weights: never bit-exact for uint8)."""
+    (in_h, in_w), (out_h, out_w) = shape
+    img = _input(dtype, in_h, in_w, channels, seed=in_h * 1000 + in_w + channels + 11)
+    x = torch.from_numpy(img).to(DEV)
+    outs = []
+    for t in AA_TILES:
+        y = xr.resize(x, (out_h, out_w), mode, tile=t)
+        torch.cuda.synchronize()
+        outs.append(y.cpu().numpy())
+    compare(outs[0], img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o.view(np.uint8), outs[0].view(np.uint8))
+
+
+@pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
+def test_antialiased_bands_and_limits(mode):
+    img = fields.field_unit(120, 64, 4, seed=3, dtype=np.float32)
+    out_h, out_w = 37, 29
+    whole = _gpu(img, out_h, out_w, mode)
+    x = torch.from_numpy(img).to(DEV)
+    bands = []
+    for row0, row1 in [(0, 10), (10, 11), (11, 37)]:
+        first, last = xr.needed_rows(120, out_h, row0, row1 - row0, mode)
+        dst = torch.empty((row1 - row0, out_w, 4), dtype=x.dtype, device=DEV)
+        xr.resize_into(x[first:last + 1].contiguous(), dst, mode, src_row0=first, src_height=120,
+                       dst_row0=row0, dst_height=out_h)
+        bands.append(dst)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(torch.cat(bands).cpu().numpy().view(np.uint32), whole.view(np.uint32))
+    # weight tables beyond the LDS budget are refused
+    big = torch.zeros((8, 30000), dtype=torch.float32, device=DEV)
+    with pytest.raises(xr.XResizeError) as e:
+        xr.resize(big, (8, 10), mode, tile=xr.tile(xr.XR_KERNEL_GATHER, 256, 1))
+    assert e.value.code == 11
+    with pytest.raises(xr.XResizeError) as e:  # pixel-centre map only
+        xr.resize(x, (out_h, out_w), mode, mapping="paper")
+    assert e.value.code == 11
 
 
 LDS_CASES = [
