@@ -329,10 +329,12 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         chans = src0.shape[-1] if layout == "hwc" and src0.dim() == 3 else 1
         in_hw = src0.shape[:2] if layout == "hwc" else src0.shape[-2:]
         out_hw = out_shape[:2] if layout == "hwc" else out_shape[-2:]
-        cands = [c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], chans, in_hw[1], in_hw[0],
-                                               out_hw[1], out_hw[0])
-                 if c.kernel in ((xr.XR_KERNEL_GATHER,) if mode.endswith("_aa")
-                                 else (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS))]
+        # the antialiased filters: the library's own list (gather and LDS
+        # blocks, those whose LDS fits); the others: strip shapes
+        cands = None if mode.endswith("_aa") else [
+            c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], chans, in_hw[1], in_hw[0],
+                                          out_hw[1], out_hw[0])
+            if c.kernel in (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS)]
         tile, _ = xr.autotune(srcs, dsts, mode, layout=layout, candidates=cands, reps=4, groups=3)
 
         def launch(i):

@@ -117,7 +117,9 @@ typedef struct {
  *                               64 up to 512, ppt_x = 4 for 4 channels and 8
  *                               for one). XR_ERR_ARG when one workgroup's row
  *                               segment does not fit its LDS budget (strong
- *                               downscales with wide workgroups)
+ *                               downscales with wide workgroups). With the
+ *                               antialiased filters of xr_resize: the
+ *                               LDS-tiled separable kernel (see there)
  *  order  = 0 : tiles are processed in launch order (row-major)
  *         = 1 : the launch is split into 8 contiguous bands of tiles, one per
  *               XCD (the hardware deals workgroups to the 8 XCDs in turn), so
@@ -169,11 +171,19 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
  *            convention): the filter stretched by sigma = max(1, N_in/N_out),
  *            taps |i - s| < R sigma (R = 1, 2) inside the image (dropped, not
  *            clamped, at the edges), weights K((i - s)/sigma) divided by their
- *            sum (float32). Pixel-centre map only. Always one pixel per thread
- *            in a block of the tile's block_w x block_h (a gather tile; other
- *            kinds use 64 x 4); XR_ERR_ARG when the workgroup's weight tables,
- *            4 (2 bw + 2 bh + bw kx + bh ky) bytes with k = floor(2 R sigma) + 1,
- *            exceed 64 KiB.
+ *            sum (float32). Pixel-centre map only. One output pixel per thread
+ *            in a block of block_w x block_h threads (ppt 1 x 1, order 0):
+ *            XR_KERNEL_GATHER reads every tap from global memory;
+ *            XR_KERNEL_STRIP_LDS stages the block's source window in LDS and
+ *            filters it separably (rows, then columns). Both give identical
+ *            bits. Strip kinds (and XR_KERNEL_AUTO before tuning) take the
+ *            first LDS block of 64x4, 64x2, 32x2, 16x2 that fits, else a 64x4
+ *            gather. XR_ERR_ARG when the workgroup's LDS exceeds 64 KiB: the
+ *            weight tables, 4 (2 bw + 2 bh + bw kx + bh ky) bytes with
+ *            k = floor(2 R sigma) + 1, plus for LDS blocks the source window
+ *            (W x H pixels, W = floor(((bw - 1) N_in + 2 R max(N_in, N_out)) / N_out) + 2
+ *            clipped to the width, H likewise) and an H x bw x channels float32
+ *            row buffer.
  *  mapping = XR_MAP_HALF_PIXEL (as xr_resize_bilinear / _bicubic) or
  *            XR_MAP_PAPER: s = x N_in / N_out, the map of eq. 1 as printed
  *            (x_p = x_f / scale with scale = N_out / N_in from the sizes);

@@ -394,18 +394,51 @@ int check_lds(const xr_tile &t, int32_t filter, int32_t dtype, int32_t channels,
     return XR_OK;
 }
 
+int64_t aa_lds_bytes(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
+{
+    const int32_t r = aa_radius(filter);
+    if (t.kernel == XR_KERNEL_STRIP_LDS)
+        return xr::aa_tile_plan(src.width, src.height, dst.width, dst.height, r, t.block_w, t.block_h,
+                                elem_size(src.dtype) * src.channels, src.channels)
+            .lds_bytes;
+    return xr::aa_plan(src.width, src.height, dst.width, dst.height, r, t.block_w, t.block_h).lds_bytes;
+}
+
+// The antialiased filters take a gather tile (k_gather_aa) or an LDS tile
+// (k_tile_aa): block_w x block_h threads, one output pixel each.
 int check_aa(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
 {
     if (!is_aa(filter))
         return XR_OK;
-    const xr::AaPlan p = xr::aa_plan(src.width, src.height, dst.width, dst.height, aa_radius(filter),
-                                     t.block_w, t.block_h);
-    if (p.lds_bytes > xr::kAaLdsBudget)
+    if (t.kernel != XR_KERNEL_GATHER && t.kernel != XR_KERNEL_STRIP_LDS)
+        return fail(XR_ERR_ARG, "the antialiased filters take XR_KERNEL_GATHER or XR_KERNEL_STRIP_LDS tiles");
+    if (t.block_w < 1 || t.block_h < 1 || t.block_w * t.block_h > 1024 || t.ppt_x != 1 || t.ppt_y != 1 ||
+        t.order != 0)
         return fail(XR_ERR_ARG,
-                    "antialiased resize: weight tables of a %dx%d block (%d x %d taps) need %lld bytes "
-                    "of LDS (limit %lld); use a smaller block", t.block_w, t.block_h, p.kx, p.ky,
-                    static_cast<long long>(p.lds_bytes), static_cast<long long>(xr::kAaLdsBudget));
+                    "antialiased tile %dx%d (ppt %dx%d, order %d) invalid: need 1..1024 threads, ppt 1x1, "
+                    "order 0", t.block_w, t.block_h, t.ppt_x, t.ppt_y, t.order);
+    const int64_t bytes = aa_lds_bytes(t, filter, src, dst);
+    if (bytes > xr::kAaLdsBudget)
+        return fail(XR_ERR_ARG,
+                    "antialiased resize: a %dx%d %s block needs %lld bytes of LDS (limit %lld); use a "
+                    "smaller block%s", t.block_w, t.block_h,
+                    t.kernel == XR_KERNEL_GATHER ? "gather" : "LDS", static_cast<long long>(bytes),
+                    static_cast<long long>(xr::kAaLdsBudget),
+                    t.kernel == XR_KERNEL_GATHER ? "" : " or a gather tile");
     return XR_OK;
+}
+
+// Default antialiased tile: the LDS kernel with the first block whose
+// window fits, else the gather.
+xr_tile aa_default_tile(int32_t filter, const xr_image &src, const xr_image &dst)
+{
+    const int blocks[][2] = {{64, 4}, {64, 2}, {32, 2}, {16, 2}};
+    for (const auto &b : blocks) {
+        const xr_tile t{XR_KERNEL_STRIP_LDS, b[0], b[1], 1, 1, 0};
+        if (aa_lds_bytes(t, filter, src, dst) <= xr::kAaLdsBudget)
+            return t;
+    }
+    return xr_tile{XR_KERNEL_GATHER, 64, 4, 1, 1, 0};
 }
 
 bool lds_usable(const xr_tile &t, int32_t filter, const xr_image &src, const xr_image &dst)
@@ -424,9 +457,12 @@ xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, c
     auto it = g_tuned.find(key);
     // a tuned LDS shape applies only to sources it can stage (alignment is
     // not part of the key)
-    if (it != g_tuned.end() &&
-        (it->second.kernel != XR_KERNEL_STRIP_LDS || lds_usable(it->second, filter, src, dst)))
-        return it->second;
+    if (it != g_tuned.end()) {
+        const xr_tile &tt = it->second;
+        if (is_aa(filter) ? aa_lds_bytes(tt, filter, src, dst) <= xr::kAaLdsBudget
+                          : (tt.kernel != XR_KERNEL_STRIP_LDS || lds_usable(tt, filter, src, dst)))
+            return tt;
+    }
     return default_tile(src.channels, src.width, src.height, dst.width, dst.rows, dst.height,
                         dst.planes);
 }
@@ -448,18 +484,22 @@ int resize_common(const xr_image *src, const xr_image *dst, const xr_tile *tile,
     if (rc)
         return rc;
     xr_tile t = resolve_tile(tile, filter, *src, *dst);
-    if (is_aa(filter) && t.kernel != XR_KERNEL_GATHER)
-        t = xr_tile{XR_KERNEL_GATHER, 64, 4, 1, 1, 0};  // the antialiased kernel is a gather
-    rc = check_tile(t, src->dtype, src->channels);
-    if (rc)
-        return rc;
-    rc = check_aa(t, filter, *src, *dst);
+    if (is_aa(filter)) {
+        // strip shapes (and the untuned default) mean the default antialiased tile
+        if (t.kernel == XR_KERNEL_STRIP || t.kernel == XR_KERNEL_STRIP_ANY ||
+            (t.kernel == XR_KERNEL_STRIP_LDS && (t.ppt_x != 1 || t.ppt_y != 1)))
+            t = aa_default_tile(filter, *src, *dst);
+        rc = check_aa(t, filter, *src, *dst);
+    } else {
+        rc = check_tile(t, src->dtype, src->channels);
+    }
     if (rc)
         return rc;
     rc = check_grid(t, *dst);
     if (rc)
         return rc;
-    rc = check_lds(t, filter, src->dtype, src->channels, src->width, dst->width, src_aligned4(*src));
+    if (!is_aa(filter))
+        rc = check_lds(t, filter, src->dtype, src->channels, src->width, dst->width, src_aligned4(*src));
     if (rc)
         return rc;
     const xr::ResizeArgs a = make_args(*src, *dst, mapping);
@@ -798,7 +838,11 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
                              {128, 2}, {256, 1}};
     for (const auto &g : gather)
         c.push_back(xr_tile{XR_KERNEL_GATHER, g[0], g[1], 1, 1, 0});
-    if (is_aa(filter)) {  // the antialiased kernel is a gather: block shapes only
+    if (is_aa(filter)) {  // the antialiased kernels: gather and LDS block shapes, one pixel each
+        const int lds_blocks[][2] = {{16, 16}, {32, 8}, {64, 4}, {128, 2}, {32, 16}, {64, 8},
+                                     {128, 4}, {64, 16}, {256, 4}, {64, 2}, {32, 2}, {16, 2}};
+        for (const auto &b : lds_blocks)
+            c.push_back(xr_tile{XR_KERNEL_STRIP_LDS, b[0], b[1], 1, 1, 0});
         if (out)
             for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)
                 out[k] = c[k];
@@ -874,11 +918,8 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
             cand.erase(std::remove_if(cand.begin(), cand.end(),
                                       [&](const xr_tile &t) {
                                           if (is_aa(filter))
-                                              return xr::aa_plan(srcs[k].width, srcs[k].height,
-                                                                 dsts[k].width, dsts[k].height,
-                                                                 aa_radius(filter), t.block_w,
-                                                                 t.block_h)
-                                                         .lds_bytes > xr::kAaLdsBudget;
+                                              return aa_lds_bytes(t, filter, srcs[k], dsts[k]) >
+                                                     xr::kAaLdsBudget;
                                           return t.kernel == XR_KERNEL_STRIP_LDS &&
                                                  !lds_usable(t, filter, srcs[k], dsts[k]);
                                       }),
@@ -887,16 +928,18 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
     for (size_t k = 0; k < cand.size(); ++k) {
         if (cand[k].kernel == XR_KERNEL_AUTO)
             return fail(XR_ERR_ARG, "candidate %zu is XR_KERNEL_AUTO", k);
-        rc = check_tile(cand[k], src->dtype, src->channels);
+        if (is_aa(filter)) {
+            for (int32_t j = 0; j < n_pairs && !rc; ++j)
+                rc = check_aa(cand[k], filter, srcs[j], dsts[j]);
+        } else {
+            rc = check_tile(cand[k], src->dtype, src->channels);
+            if (!rc)
+                rc = check_lds(cand[k], filter, src->dtype, src->channels, src->width, dst->width,
+                               std::all_of(srcs, srcs + n_pairs,
+                                           [](const xr_image &i) { return src_aligned4(i); }));
+        }
         if (!rc)
             rc = check_grid(cand[k], *dst);
-        if (!rc)
-            rc = check_lds(cand[k], filter, src->dtype, src->channels, src->width, dst->width,
-                           std::all_of(srcs, srcs + n_pairs, [](const xr_image &i) { return src_aligned4(i); }));
-        if (!rc && is_aa(filter) && cand[k].kernel != XR_KERNEL_GATHER)
-            rc = fail(XR_ERR_ARG, "the antialiased filters take gather tiles");
-        if (!rc)
-            rc = check_aa(cand[k], filter, *src, *dst);
         if (rc)
             return fail(rc, "candidate %zu: %s", k, g_last_error.c_str());
     }

@@ -317,6 +317,99 @@ __device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned ch
     }
 }
 
+// The antialiased filter on a block_w x block_h tile of output pixels with
+// the source window staged in LDS (separable): the same weight tables as
+// k_gather_aa; then the tile's source window (rows ylo(first) .. yhi(last),
+// columns xlo(first) .. xhi(last)) is copied to LDS with coalesced loads; the
+// horizontal pass filters every window row for every tile column into an LDS
+// row buffer; each thread then sums its rows. Per pixel the float32
+// sequence is exactly k_gather_aa's (taps ascending per row, rows ascending),
+// so the two kernels agree bit for bit. The window is at most win_w x win_h
+// pixels (bounded on the host from the scale).
+template <int R, typename T, int C>
+__global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int32_t ky, int32_t win_w,
+                                                  int32_t win_h)
+{
+    constexpr int PB = Pix<T, C>::kBytes;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int32_t bw = static_cast<int32_t>(blockDim.x), bh = static_cast<int32_t>(blockDim.y);
+    const int32_t nthreads = bw * bh;
+    int32_t *xlo = reinterpret_cast<int32_t *>(lds);
+    int32_t *xn = xlo + bw;
+    int32_t *ylo = xn + bw;
+    int32_t *yn = ylo + bh;
+    float *xw = reinterpret_cast<float *>(yn + bh);
+    float *yw = xw + bw * kx;
+    const int64_t table_bytes = 4 * (2 * static_cast<int64_t>(bw) + 2 * bh +
+                                     static_cast<int64_t>(bw) * kx + static_cast<int64_t>(bh) * ky);
+    unsigned char *win = lds + (table_bytes + 15) / 16 * 16;
+    float *hbuf = reinterpret_cast<float *>(win + (static_cast<int64_t>(win_w) * win_h * PB + 15) / 16 * 16);
+    const int32_t tid = threadIdx.y * bw + threadIdx.x;
+    for (int32_t t = tid; t < bw + bh; t += nthreads) {
+        if (t < bw) {
+            const int32_t x = min(static_cast<int32_t>(blockIdx.x) * bw + t, a.out_w - 1);
+            aa_table<R>(x, a.in_w, a.out_w, kx, xlo + t, xn + t, xw + t * kx);
+        } else {
+            const int32_t u = t - bw;
+            const int32_t y = a.dst_row0 + min(static_cast<int32_t>(blockIdx.y) * bh + u, a.dst_rows - 1);
+            aa_table<R>(y, a.in_h, a.out_h, ky, ylo + u, yn + u, yw + u * ky);
+        }
+    }
+    __syncthreads();
+    // the tile's source window (tap ranges are monotone in x and y)
+    const int32_t wx0 = xlo[0];
+    const int32_t ww = min(xlo[bw - 1] + xn[bw - 1] - wx0, win_w);
+    const int32_t wy0 = ylo[0];
+    const int32_t wh = min(ylo[bh - 1] + yn[bh - 1] - wy0, win_h);
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
+    for (int32_t i = tid; i < ww * wh; i += nthreads) {
+        const int32_t r = i / ww, c = i - r * ww;
+        const unsigned char *row = src + static_cast<int64_t>(wy0 + r - a.src_row0) * a.src_pitch;
+        copy_pixel<PB>(win + (static_cast<int64_t>(r) * win_w + c) * PB,
+                       row + static_cast<int64_t>(wx0 + c) * PB);
+    }
+    __syncthreads();
+    // horizontal pass: window row r, tile column c
+    for (int32_t i = tid; i < wh * bw; i += nthreads) {
+        const int32_t r = i / bw, c = i - r * bw;
+        const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
+        const int32_t x0 = xlo[c] - wx0, nx = xn[c];
+        const float *wxr = xw + c * kx;
+        float h[C], p[C];
+        Pix<T, C>::load(wrow, x0, p);
+        fma_first(h, wxr[0], p);
+        for (int32_t k = 1; k < nx; ++k) {
+            Pix<T, C>::load(wrow, x0 + k, p);
+            fma_next(h, wxr[k], p);
+        }
+        float *hp = hbuf + (static_cast<int64_t>(r) * bw + c) * C;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            hp[ch] = h[ch];
+    }
+    __syncthreads();
+    const int32_t px = blockIdx.x * bw + threadIdx.x;
+    const int32_t py = blockIdx.y * bh + threadIdx.y;
+    if (px >= a.out_w || py >= a.dst_rows)
+        return;
+    const int32_t r0 = ylo[threadIdx.y] - wy0, ny = yn[threadIdx.y];
+    const float *wyr = yw + threadIdx.y * ky;
+    float acc[C], h[C];
+    for (int32_t j = 0; j < ny; ++j) {
+        const float *hp = hbuf + (static_cast<int64_t>(r0 + j) * bw + threadIdx.x) * C;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            h[ch] = hp[ch];
+        if (j == 0)
+            fma_first(acc, wyr[0], h);
+        else
+            fma_next(acc, wyr[j], h);
+    }
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                         static_cast<int64_t>(py) * a.dst_pitch;
+    Pix<T, C>::store(dst, px, acc);
+}
+
 // Any scale: a thread owns PPX adjacent output columns (each with its own
 // taps) and walks the source rows its strip of output rows reads, in order.
 // Each source row is filtered once into ring slot (row - first row) mod K;
@@ -1330,11 +1423,18 @@ namespace {
 template <int R, typename T, int C>
 hipError_t launch_aa_typed(const ResizeArgs &a, const xr_tile &tile, hipStream_t stream)
 {
-    const AaPlan plan = aa_plan(a.in_w, a.in_h, a.out_w, a.out_h, R, tile.block_w, tile.block_h);
     const dim3 block(tile.block_w, tile.block_h, 1);
     const dim3 grid((a.out_w + tile.block_w - 1) / tile.block_w,
                     (a.dst_rows + tile.block_h - 1) / tile.block_h, a.planes);
-    hipLaunchKernelGGL((k_gather_aa<R, T, C>), grid, block, plan.lds_bytes, stream, a, plan.kx, plan.ky);
+    if (tile.kernel == XR_KERNEL_GATHER) {
+        const AaPlan plan = aa_plan(a.in_w, a.in_h, a.out_w, a.out_h, R, tile.block_w, tile.block_h);
+        hipLaunchKernelGGL((k_gather_aa<R, T, C>), grid, block, plan.lds_bytes, stream, a, plan.kx, plan.ky);
+    } else {
+        const AaPlan plan = aa_tile_plan(a.in_w, a.in_h, a.out_w, a.out_h, R, tile.block_w, tile.block_h,
+                                         Pix<T, C>::kBytes, C);
+        hipLaunchKernelGGL((k_tile_aa<R, T, C>), grid, block, plan.lds_bytes, stream, a, plan.kx, plan.ky,
+                           plan.win_w, plan.win_h);
+    }
     return hipGetLastError();
 }
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "../../include/xresize.h"
 
 namespace xr {
@@ -76,6 +78,7 @@ bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels);
 struct AaPlan {
     int32_t kx, ky;
     int64_t lds_bytes;
+    int32_t win_w = 0, win_h = 0;  // source window of the LDS-tiled kernel
 };
 inline AaPlan aa_plan(int32_t in_w, int32_t in_h, int32_t out_w, int32_t out_h, int32_t r,
                       int32_t block_w, int32_t block_h)
@@ -91,6 +94,25 @@ inline AaPlan aa_plan(int32_t in_w, int32_t in_h, int32_t out_w, int32_t out_h, 
     return p;
 }
 constexpr int64_t kAaLdsBudget = 64 * 1024;
+// The LDS-tiled antialiased kernel adds the tile's source window (pixels of
+// pb bytes) and one float32 row buffer per window row: a block of bw output
+// columns reads at most floor(((bw - 1) n_in + 2 R max(n_in, n_out)) / n_out) + 2
+// source columns (its first and last columns' tap ranges, eq. 1).
+inline AaPlan aa_tile_plan(int32_t in_w, int32_t in_h, int32_t out_w, int32_t out_h, int32_t r,
+                           int32_t block_w, int32_t block_h, int32_t pb, int32_t channels)
+{
+    AaPlan p = aa_plan(in_w, in_h, out_w, out_h, r, block_w, block_h);
+    const auto span = [r](int64_t n, int64_t n_in, int64_t n_out) {
+        return static_cast<int32_t>(((n - 1) * n_in + 2 * r * (n_in > n_out ? n_in : n_out)) / n_out + 2);
+    };
+    p.win_w = std::min<int32_t>(span(block_w, in_w, out_w), in_w);
+    p.win_h = std::min<int32_t>(span(block_h, in_h, out_h), in_h);
+    const int64_t tables = (p.lds_bytes + 15) / 16 * 16;
+    const int64_t window = (static_cast<int64_t>(p.win_w) * p.win_h * pb + 15) / 16 * 16;
+    const int64_t rows = static_cast<int64_t>(p.win_h) * block_w * channels * 4;
+    p.lds_bytes = tables + window + rows;
+    return p;
+}
 
 // Pixels per thread along x that the strip kernel is instantiated for.
 bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx);

@@ -190,7 +190,10 @@ AA_SHAPES = [
     ((5, 9), (12, 20)),       # grow: edges renormalised
 ]
 AA_TILES = [None, xr.tile(xr.XR_KERNEL_GATHER, 8, 8), xr.tile(xr.XR_KERNEL_GATHER, 32, 4),
-            xr.tile(xr.XR_KERNEL_GATHER, 256, 1), xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 4, 7)]
+            xr.tile(xr.XR_KERNEL_GATHER, 256, 1), xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 4, 7),
+            xr.tile(xr.XR_KERNEL_STRIP_LDS, 16, 2, 1, 1), xr.tile(xr.XR_KERNEL_STRIP_LDS, 64, 4, 1, 1),
+            xr.tile(xr.XR_KERNEL_STRIP_LDS, 16, 16, 1, 1), xr.tile(xr.XR_KERNEL_STRIP_LDS, 128, 2, 1, 1),
+            xr.tile(xr.XR_KERNEL_STRIP_LDS, 7, 3, 1, 1)]
 
 
 @pytest.mark.parametrize("shape", AA_SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
@@ -198,20 +201,57 @@ AA_TILES = [None, xr.tile(xr.XR_KERNEL_GATHER, 8, 8), xr.tile(xr.XR_KERNEL_GATHE
 @pytest.mark.parametrize("channels", [1, 4])
 @pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
 def test_antialiased(shape, dtype, channels, mode):
-    """The antialiased kernel: every block shape bitwise equal (a strip tile
-    runs the same gather), within the storage rule of the FP64 antialiased
-    oracle (float32 weights: never bit-exact for uint8)."""
+    """The antialiased kernels (gather and LDS-tiled): every block shape
+    bitwise equal (a strip tile means the default tile), within the storage
+    rule of the FP64 antialiased oracle (float32 weights: never bit-exact for
+    uint8). An LDS block whose source window exceeds the budget is refused;
+    the 16 x 2 one fits every shape here."""
     (in_h, in_w), (out_h, out_w) = shape
     img = _input(dtype, in_h, in_w, channels, seed=in_h * 1000 + in_w + channels + 11)
     x = torch.from_numpy(img).to(DEV)
     outs = []
     for t in AA_TILES:
-        y = xr.resize(x, (out_h, out_w), mode, tile=t)
+        try:
+            y = xr.resize(x, (out_h, out_w), mode, tile=t)
+        except xr.XResizeError as e:
+            assert t is not None and t.kernel == xr.XR_KERNEL_STRIP_LDS and (t.block_w, t.block_h) != (16, 2)
+            assert e.code == 11 and "LDS" in str(e)
+            continue
         torch.cuda.synchronize()
         outs.append(y.cpu().numpy())
     compare(outs[0], img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
     for o in outs[1:]:
         np.testing.assert_array_equal(o.view(np.uint8), outs[0].view(np.uint8))
+
+
+AA_WIDE = [
+    ((1000, 1234), (250, 301), np.uint8, 4, "bilinear_aa"),   # ~x0.25, ragged blocks
+    ((777, 1500), (389, 751), np.float16, 4, "bicubic_aa"),   # ~x0.5
+    ((640, 2048), (91, 300), np.float32, 1, "bicubic_aa"),    # ~x1/7
+    ((300, 400), (500, 900), np.uint8, 1, "bilinear_aa"),     # upscale: plain taps
+]
+
+
+@pytest.mark.parametrize("case", AA_WIDE, ids=lambda c: f"{c[0][1]}-{c[1][1]}-c{c[3]}-{c[4]}")
+def test_antialiased_tiled_matches_gather_on_many_blocks(case):
+    """LDS-tiled and gather kernels bitwise equal over many workgroups with
+    ragged right and bottom blocks; sampled rows against the oracle."""
+    (in_h, in_w), (out_h, out_w), dtype, channels, mode = case
+    img = _input(dtype, in_h, in_w, channels, seed=in_w + 7 * channels)
+    x = torch.from_numpy(img).to(DEV)
+    ref = xr.resize(x, (out_h, out_w), mode, tile=xr.tile(xr.XR_KERNEL_GATHER, 64, 4))
+    for bw, bh in [(64, 4), (32, 8), (16, 2), (48, 5)]:
+        try:
+            y = xr.resize(x, (out_h, out_w), mode, tile=xr.tile(xr.XR_KERNEL_STRIP_LDS, bw, bh, 1, 1))
+        except xr.XResizeError as e:
+            assert e.code == 11 and (bw, bh) != (16, 2)
+            continue
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(y.cpu().numpy().view(np.uint8), ref.cpu().numpy().view(np.uint8))
+    torch.cuda.synchronize()
+    got = ref.cpu().numpy()
+    rows = sorted({0, 1, out_h // 3, out_h - 2, out_h - 1})
+    compare(got[rows], img, out_h, out_w, MODES[mode], rows=rows, what=f"{case}")
 
 
 @pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
