@@ -367,21 +367,27 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
             (1024, 1024), "bilinear")
     measure("c4_bilinear_x2_f32_nchw_fwd", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
             (32, 3, 2048, 2048), "bilinear", layout="nchw")
-    # C4 adjoint
-    g = torch.randn((32, 3, 2048, 2048), device=dev)
-    gs = torch.empty((32, 3, 1024, 1024), device=dev)
+    # C4 adjoint (exact x2 float32: register walk), and the owner-computes
+    # kernel: float16 gradients at x2, float32 at a non-dyadic scale
+    def adjoint(name, g_shape, in_hw, mode, dtype):
+        g = torch.randn(g_shape, device=dev).to(dtype)
+        gs = torch.empty(g_shape[:2] + in_hw, device=dev, dtype=dtype)
 
-    def bwd(i):
-        xr.resize_backward(g, (1024, 1024), "bilinear", out=gs)
+        def bwd(i):
+            xr.resize_backward(g, in_hw, mode, out=gs)
 
-    wall, ms = time_launches(bwd, 1, 20, 3, torch)
-    k_s = sum(ms) / len(ms) / 1e3
-    alg = (g.numel() + gs.numel()) * 4
-    out["c4_bilinear_x2_f32_nchw_adjoint"] = {"ms": round(k_s * 1e3, 4), "gbs": round(alg / k_s / 1e9, 1),
-                                              "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4)}
-    log(f"extra adjoint: {out['c4_bilinear_x2_f32_nchw_adjoint']}")
-    del g, gs
-    torch.cuda.empty_cache()
+        wall, ms = time_launches(bwd, 1, 20, 3, torch)
+        k_s = sum(ms) / len(ms) / 1e3
+        alg = (g.numel() + gs.numel()) * g.element_size()
+        out[name] = {"ms": round(k_s * 1e3, 4), "gbs": round(alg / k_s / 1e9, 1),
+                     "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"extra {name}: {out[name]}")
+        del g, gs
+        torch.cuda.empty_cache()
+
+    adjoint("c4_bilinear_x2_f32_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear", torch.float32)
+    adjoint("bilinear_x2_f16_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear", torch.float16)
+    adjoint("bicubic_x1.5_f32_nchw_adjoint", (32, 3, 1536, 1536), (1024, 1024), "bicubic", torch.float32)
     # C5: 16384^2 FP16 -> 32768^2, whole image and 16 row bands
     src = torch.clamp(fields.smooth_field_torch(16384, 16384, 1, 1005, dev)[:, :, 0] / 255.0, 0, 1).half()
     dst = torch.empty((32768, 32768), dtype=torch.float16, device=dev)

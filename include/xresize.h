@@ -248,14 +248,17 @@ int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candida
  * Adjoint of the resize with respect to its input: grad_src = A^T grad_dst,
  * where A is the linear map of the forward call with the same filter and
  * sizes; every output pixel scatters wy_j * wx_i * g onto its clamped taps
- * (the transpose of eq. 5). float32, whole images only (row0 = 0,
- * rows = height on both), planes map one to one, channels 1 or 4.
- * grad_src is OVERWRITTEN: each workgroup owns a tile of grad_src, scatter-adds
- * the contributions of every output pixel that touches the tile into LDS
- * (LDS float atomics) and stores the tile once, so no global atomics are used.
- * The order in which LDS contributions are summed (not the set of terms) may
- * differ between runs. XR_ERR_SHAPE if the vertical upscale is too strong for
- * one tile (more than about 190x).
+ * (the transpose of eq. 5). Gradients stored as float32 or float16 (both
+ * images of one type; XR_ERR_DTYPE otherwise), summed in float32 and rounded
+ * once to the storage type. Whole images only (row0 = 0, rows = height on
+ * both), planes map one to one, channels 1 or 4.
+ * grad_src is OVERWRITTEN: each workgroup owns a tile of grad_src, gathers the
+ * contributions of every output pixel that touches the tile (rows of the
+ * horizontal adjoint in LDS, then columns) and stores the tile once: no
+ * atomics, no clearing pass. Every sum runs in a fixed order, so the result
+ * is deterministic. Exact x2 in float32 takes a register walk plus a border
+ * pass instead (also deterministic). XR_ERR_SHAPE if the upscale is too
+ * strong for one tile (rows beyond about 190x, columns beyond a few hundred x).
  */
 int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32_t filter,
                        void *stream);

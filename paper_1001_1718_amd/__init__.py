@@ -160,7 +160,8 @@ def resize(x: torch.Tensor, size, mode="bilinear", layout="hwc", tile=None, stre
 
 def resize_backward(grad_out: torch.Tensor, in_size, mode="bilinear", layout="nchw",
                     out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-    """Adjoint of ``resize`` w.r.t. its input (float32): returns A^T grad_out."""
+    """Adjoint of ``resize`` w.r.t. its input (float32 or float16 gradients,
+    summed in float32): returns A^T grad_out in grad_out's dtype."""
     in_h, in_w = int(in_size[0]), int(in_size[1])
     g = grad_out.contiguous()
     if out is None:
@@ -181,7 +182,7 @@ def resize_backward(grad_out: torch.Tensor, in_size, mode="bilinear", layout="nc
 
 
 class ResizeFn(torch.autograd.Function):
-    """Differentiable resize of float32 NCHW tensors w.r.t. the input."""
+    """Differentiable resize of float32 or float16 NCHW tensors w.r.t. the input."""
 
     @staticmethod
     def forward(ctx, x, size, mode="bilinear"):

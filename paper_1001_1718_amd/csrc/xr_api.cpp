@@ -797,8 +797,9 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
     rc = check_image(grad_src, "grad_src");
     if (rc)
         return rc;
-    if (grad_dst->dtype != XR_F32 || grad_src->dtype != XR_F32)
-        return fail(XR_ERR_DTYPE, "the adjoint is float32 only");
+    if ((grad_dst->dtype != XR_F32 && grad_dst->dtype != XR_F16) || grad_src->dtype != grad_dst->dtype)
+        return fail(XR_ERR_DTYPE, "the adjoint takes float32 or float16 gradients, both of one type "
+                    "(grad_dst %d, grad_src %d)", grad_dst->dtype, grad_src->dtype);
     if (grad_dst->channels != grad_src->channels)
         return fail(XR_ERR_CHANNELS, "grad_dst.channels %d != grad_src.channels %d",
                     grad_dst->channels, grad_src->channels);
@@ -819,9 +820,10 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
     a.dst_pitch = grad_src->row_pitch;
     a.dst_plane_pitch = grad_src->planes > 1 ? grad_src->plane_pitch : 0;
     if (!xr::backward_supported(a, filter, grad_src->channels))
-        return fail(XR_ERR_SHAPE, "adjoint: %d -> %d rows is too strong an upscale for one LDS tile",
-                    grad_src->height, grad_dst->height);
-    const hipError_t e = xr::launch_backward(a, filter, grad_src->channels, static_cast<hipStream_t>(stream));
+        return fail(XR_ERR_SHAPE, "adjoint: %dx%d -> %dx%d is too strong an upscale for one LDS tile",
+                    grad_src->width, grad_src->height, grad_dst->width, grad_dst->height);
+    const hipError_t e = xr::launch_backward(a, filter, grad_src->dtype, grad_src->channels,
+                                             static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "backward launch");
     return XR_OK;

@@ -1,4 +1,5 @@
-// Adjoint of the resize with respect to its input, float32, for gfx950.
+// Adjoint of the resize with respect to its input for gfx950: gradients
+// stored as float32 or float16, summed in float32.
 //
 // grad_src = A_y^T grad_dst A_x: every output pixel (y, x) scatters
 // wy_j * wx_i * g[y][x] onto its clamped taps (the transpose of eq. 5).
@@ -8,16 +9,17 @@
 // pixel is written exactly once with a plain store: no global atomics, no
 // clearing pass, and pixels no output touches come out as zero.
 //
-//  phase 0  taps (first row, K weights) of the output rows of the region;
-//  phase 1  horizontal adjoint, scatter-add in LDS: for every output pixel of
-//           the region, u[y][c] += wx_i(x) * g[y][x] on each tap c inside the
-//           tile (LDS float atomics, the only atomics of the kernel);
+//  phase 0  taps (first row, K weights) of the output rows of the region,
+//           and for each tile column c the outputs x whose taps reach it with
+//           their summed weight w(x, c);
+//  phase 1  horizontal adjoint, gather: u[y][c] = sum over x ascending of
+//           w(x, c) * g[y][x];
 //  phase 2  vertical adjoint, gather: grad[r][c] = sum over the output rows y
 //           whose taps include r of wy_j(y) * u[y][c], summed in ascending y.
 //
-// Floating-point order: each tile sums its LDS contributions in whatever
-// order the LDS atomics land, so results can differ between runs in the last
-// bits; the set of terms is exact.
+// Every sum has a fixed order, so the result is deterministic (bit for bit
+// the same on every run and for every tiling of the launch). The exact-x2
+// float32 path below is deterministic as well.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -69,12 +71,14 @@ __device__ __forceinline__ int32_t last_output(int32_t c, int32_t n_in, int32_t 
     return static_cast<int32_t>(x < 0 ? 0 : (x > n_out - 1 ? n_out - 1 : x));
 }
 
-// a.src = grad_dst (out_w x out_h), a.dst = grad_src (in_w x in_h).
-// Tile: tw columns x th rows of grad_src; LDS holds max_rows x tw x C floats
-// of u plus max_rows x (K + 1) words of row taps.
-template <int FILTER, int C>
+// a.src = grad_dst (out_w x out_h), a.dst = grad_src (in_w x in_h), both
+// stored as T (float or _Float16), summed in float32.
+// Tile: tw columns x th rows of grad_src. LDS holds max_rows x tw x C floats
+// of u, max_rows x (K + 1) words of row taps, and per tile column the first
+// output column, the count and nmax weights of the outputs that reach it.
+template <int FILTER, typename T, int C>
 __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t tw, int32_t th,
-                                                           int32_t max_rows)
+                                                           int32_t max_rows, int32_t nmax)
 {
     using TP = Taps<FILTER>;
     constexpr int K = TP::K;
@@ -83,22 +87,24 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
     float *u = lds;                                                           // [max_rows][tw*C]
     int32_t *ylo = reinterpret_cast<int32_t *>(lds + max_rows * row_floats);  // [max_rows]
     float *ywt = reinterpret_cast<float *>(ylo + max_rows);                   // [max_rows][K]
+    int32_t *colx = reinterpret_cast<int32_t *>(ywt + max_rows * K);          // [tw]
+    int32_t *coln = colx + tw;                                                // [tw]
+    float *colw = reinterpret_cast<float *>(coln + tw);                       // [tw][nmax]
 
     const int32_t c_a = blockIdx.x * tw;
     const int32_t c_b = min(c_a + tw, a.in_w);
     const int32_t r_a = blockIdx.y * th;
     const int32_t r_b = min(r_a + th, a.in_h);
     const int32_t plane = blockIdx.z;
-    const int32_t xa = first_output<FILTER>(c_a, a.in_w, a.out_w);
-    const int32_t xb = last_output<FILTER>(c_b - 1, a.in_w, a.out_w);
     const int32_t ya = first_output<FILTER>(r_a, a.in_h, a.out_h);
     const int32_t yb = min(last_output<FILTER>(r_b - 1, a.in_h, a.out_h), ya + max_rows - 1);
     const int32_t nrows = yb - ya + 1;
+    const int32_t ntc = c_b - c_a;
     const int32_t tid = threadIdx.x;
 
-    // phase 0: clear u, row taps of the region
-    for (int32_t k = tid; k < nrows * row_floats; k += kBwdThreads)
-        u[k] = 0.0f;
+    // phase 0: row taps of the region; per tile column c the outputs x whose
+    // clamped taps reach c (x in [first_output(c), last_output(c)], each with
+    // at least one tap on c) and the summed weight of those taps
     for (int32_t k = tid; k < nrows; k += kBwdThreads) {
         int32_t y0;
         float t, omt;
@@ -110,64 +116,59 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
         for (int j = 0; j < K; ++j)
             ywt[k * K + j] = w[j];
     }
-    __syncthreads();
-
-    // phase 1: horizontal adjoint of every output row of the region, into LDS.
-    // A thread takes XP adjacent output columns and walks the region's rows in
-    // groups of RU, issuing the group's loads before its LDS additions so that
-    // RU rows of loads are in flight at once.
-    const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
-    constexpr int XP = (C == 4) ? 1 : 2;
-    constexpr int RU = 8;
-    for (int32_t xc = xa + tid * XP; xc <= xb; xc += kBwdThreads * XP) {
-        float wx[XP][K];
-        int32_t lc[XP][K];
-#pragma unroll
-        for (int p = 0; p < XP; ++p) {
-            const int32_t x = min(xc + p, xb);
+    for (int32_t cl = tid; cl < ntc; cl += kBwdThreads) {
+        const int32_t c = c_a + cl;
+        const int32_t xf = first_output<FILTER>(c, a.in_w, a.out_w);
+        const int32_t n = min(max(last_output<FILTER>(c, a.in_w, a.out_w) - xf + 1, 0), nmax);
+        colx[cl] = xf;
+        coln[cl] = n;
+        for (int32_t m = 0; m < n; ++m) {
             int32_t x0;
             float t, omt;
-            axis_tap(x, a.in_w, a.out_w, 1, x0, t, omt);
-            weights<FILTER>(t, omt, wx[p]);
+            axis_tap(xf + m, a.in_w, a.out_w, 1, x0, t, omt);
+            float wx[K];
+            weights<FILTER>(t, omt, wx);
+            float w = 0.0f;
 #pragma unroll
-            for (int i = 0; i < K; ++i) {
-                const int32_t c = clampi(x0 + TP::LO + i, 0, a.in_w - 1);
-                lc[p][i] = (xc + p <= xb && c >= c_a && c < c_b) ? (c - c_a) * C : -1;
-            }
+            for (int i = 0; i < K; ++i)
+                if (clampi(x0 + TP::LO + i, 0, a.in_w - 1) == c)
+                    w += wx[i];
+            colw[cl * nmax + m] = w;
         }
-        const int32_t xl = min(xc + XP - 1, xb) - xc;  // last valid column offset
-        for (int32_t k0 = 0; k0 < nrows; k0 += RU) {
-            float g[RU][XP][C];
-#pragma unroll
-            for (int q = 0; q < RU; ++q) {
-                const int32_t row = ya + min(k0 + q, nrows - 1);
-                const unsigned char *grow = gsrc + static_cast<int64_t>(row) * a.src_pitch;
-#pragma unroll
-                for (int p = 0; p < XP; ++p)
-                    Pix<float, C>::load(grow, xc + min(p, xl), g[q][p]);
+    }
+    __syncthreads();
+
+    // phase 1: horizontal adjoint as a gather, one (region row, tile column)
+    // per thread: u[k][c] = sum over x ascending of w(x, c) g[ya + k][x]
+    const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
+    for (int32_t item = tid; item < nrows * ntc; item += kBwdThreads) {
+        const int32_t k = item / ntc, cl = item - k * ntc;
+        const unsigned char *grow = gsrc + static_cast<int64_t>(ya + k) * a.src_pitch;
+        const int32_t xf = colx[cl], n = coln[cl];
+        const float *w = colw + cl * nmax;
+        float acc[C], g[C];
+        if (n > 0) {
+            Pix<T, C>::load(grow, xf, g);
+            fma_first(acc, w[0], g);
+            for (int32_t m = 1; m < n; ++m) {
+                Pix<T, C>::load(grow, xf + m, g);
+                fma_next(acc, w[m], g);
             }
+        } else {
 #pragma unroll
-            for (int q = 0; q < RU; ++q) {
-                if (k0 + q < nrows) {
-                    float *urow = u + (k0 + q) * row_floats;
-#pragma unroll
-                    for (int p = 0; p < XP; ++p)
-#pragma unroll
-                        for (int i = 0; i < K; ++i)
-                            if (lc[p][i] >= 0) {
-#pragma unroll
-                                for (int ch = 0; ch < C; ++ch)
-                                    atomicAdd(urow + lc[p][i] + ch, wx[p][i] * g[q][p][ch]);
-                            }
-                }
-            }
+            for (int ch = 0; ch < C; ++ch)
+                acc[ch] = 0.0f;
         }
+        float *urow = u + k * row_floats + cl * C;
+#pragma unroll
+        for (int ch = 0; ch < C; ++ch)
+            urow[ch] = acc[ch];
     }
     __syncthreads();
 
     // phase 2: vertical adjoint, one (column, channel) per thread
     unsigned char *gdst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
-    const int32_t ncols = (c_b - c_a) * C;
+    const int32_t ncols = ntc * C;
     for (int32_t f = tid; f < ncols; f += kBwdThreads) {
         int32_t k_first = 0;  // first region row whose taps reach the current r
         for (int32_t r = r_a; r < r_b; ++r) {
@@ -182,7 +183,8 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
                         w += ywt[k * K + j];
                 acc = __builtin_fmaf(w, u[k * row_floats + f], acc);
             }
-            reinterpret_cast<float *>(gdst + static_cast<int64_t>(r) * a.dst_pitch)[c_a * C + f] = acc;
+            const float v[1] = {acc};
+            Pix<T, 1>::store(gdst + static_cast<int64_t>(r) * a.dst_pitch, c_a * C + f, v);
         }
     }
 }
@@ -428,9 +430,9 @@ hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
 
 // Tile of the owner-computes kernel: tw source columns (tw * C = 256 values
 // across the threads) and th source rows, shrunk until the region of output
-// rows fits the LDS budget.
+// rows and the column tables fit the LDS budget.
 struct BwdPlan {
-    int32_t tw, th, max_rows;
+    int32_t tw, th, max_rows, nmax;
     size_t lds;
 };
 
@@ -440,13 +442,17 @@ BwdPlan plan_backward(const ResizeArgs &a)
     constexpr int K = Taps<FILTER>::K;
     constexpr size_t kBudget = 64 * 1024;
     BwdPlan p{};
+    // outputs reaching one source column: at most ceil(K out / in) + 1 inside,
+    // (1 - LO + 1/2) out / in + 1 at a clamped border
+    p.nmax = static_cast<int32_t>((static_cast<int64_t>(K) * a.out_w + a.in_w - 1) / a.in_w + 2);
     p.tw = kBwdThreads / C;
     p.th = 16;
     for (;;) {
         // output rows touching th source rows: at most (th + K - 1) * out/in + 2
         const int64_t rows = (static_cast<int64_t>(p.th + K - 1) * a.out_h + a.in_h - 1) / a.in_h + 2;
         p.max_rows = static_cast<int32_t>(rows);
-        p.lds = static_cast<size_t>(rows) * (p.tw * C * sizeof(float) + (K + 1) * sizeof(int32_t));
+        p.lds = static_cast<size_t>(rows) * (p.tw * C * sizeof(float) + (K + 1) * sizeof(int32_t)) +
+                static_cast<size_t>(p.tw) * (2 + static_cast<size_t>(p.nmax)) * sizeof(float);
         if (p.lds <= kBudget)
             return p;
         if (p.th > 1) {
@@ -461,18 +467,25 @@ BwdPlan plan_backward(const ResizeArgs &a)
     }
 }
 
-template <int FILTER, int C>
+template <int FILTER, typename T, int C>
 hipError_t launch_bwd_typed(const ResizeArgs &a, hipStream_t stream)
 {
-    if (a.out_w == 2 * a.in_w && a.out_h == 2 * a.in_h)
-        return launch_bwd_up2<FILTER, C>(a, stream);
+    if constexpr (std::is_same_v<T, float>)
+        if (a.out_w == 2 * a.in_w && a.out_h == 2 * a.in_h)
+            return launch_bwd_up2<FILTER, C>(a, stream);
     const BwdPlan p = plan_backward<FILTER, C>(a);
     if (p.lds == 0)
         return hipErrorInvalidConfiguration;
     const dim3 grid((a.in_w + p.tw - 1) / p.tw, (a.in_h + p.th - 1) / p.th, a.planes);
-    hipLaunchKernelGGL((k_bwd_owner<FILTER, C>), grid, dim3(kBwdThreads), p.lds, stream, a, p.tw, p.th,
-                       p.max_rows);
+    hipLaunchKernelGGL((k_bwd_owner<FILTER, T, C>), grid, dim3(kBwdThreads), p.lds, stream, a, p.tw, p.th,
+                       p.max_rows, p.nmax);
     return hipGetLastError();
+}
+
+template <int FILTER, typename T>
+hipError_t launch_bwd_channels(const ResizeArgs &a, int32_t channels, hipStream_t stream)
+{
+    return channels == 4 ? launch_bwd_typed<FILTER, T, 4>(a, stream) : launch_bwd_typed<FILTER, T, 1>(a, stream);
 }
 
 }  // namespace
@@ -486,13 +499,14 @@ bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels)
                          : plan_backward<kBilinear, 1>(a).lds != 0;
 }
 
-hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels, hipStream_t stream)
+hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
+                           hipStream_t stream)
 {
-    if (filter == XR_BICUBIC)
-        return channels == 4 ? launch_bwd_typed<kBicubic, 4>(a, stream)
-                             : launch_bwd_typed<kBicubic, 1>(a, stream);
-    return channels == 4 ? launch_bwd_typed<kBilinear, 4>(a, stream)
-                         : launch_bwd_typed<kBilinear, 1>(a, stream);
+    if (dtype == XR_F16)
+        return filter == XR_BICUBIC ? launch_bwd_channels<kBicubic, _Float16>(a, channels, stream)
+                                    : launch_bwd_channels<kBilinear, _Float16>(a, channels, stream);
+    return filter == XR_BICUBIC ? launch_bwd_channels<kBicubic, float>(a, channels, stream)
+                                : launch_bwd_channels<kBilinear, float>(a, channels, stream);
 }
 
 }  // namespace xr

@@ -66,10 +66,11 @@ hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_
                           int32_t grid, hipStream_t stream);
 // Workgroups of the batched kernel that fit on one compute unit.
 int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads);
-hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t channels,
+hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
                            hipStream_t stream);
-// False when one source row's output rows cannot fit the adjoint's LDS tile
-// (vertical upscale beyond roughly 190x).
+// False when the adjoint's smallest LDS tile cannot hold the output rows of
+// one source row and the column tables (upscales beyond roughly 190x rows or
+// a few hundred x columns).
 bool backward_supported(const ResizeArgs &a, int32_t filter, int32_t channels);
 
 // Weight tables of the antialiased kernel: at most kx (ky) taps per output

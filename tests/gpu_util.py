@@ -11,7 +11,9 @@ Tolerances (derived in the design doc from the float32 evaluation order):
   rounding mode itself is pinned by the dyadic cases, which must be exact);
 * float16: |gpu - oracle| <= 1e-3 (values in [0, 1]) and at most one float16
   ulp away from the oracle's own float16 rounding;
-* float32: |gpu - oracle| <= 1e-5 * sum |w_y w_x v| per pixel.
+* float32: |gpu - oracle| <= 1e-5 * sum |w_y w_x v| per pixel;
+* float16 gradients (sums of unbounded size): half a float16 ulp at the
+  value's magnitude + the float32 bound.
 """
 
 import numpy as np
@@ -67,6 +69,21 @@ def check_f16(gpu: np.ndarray, ref: np.ndarray, what: str = ""):
     ulp = np.spacing(np.abs(want).astype(np.float16)).astype(np.float64)
     assert np.all(np.abs(g - want) <= ulp + 1e-30), f"{what}: more than one float16 ulp from the oracle"
     return float(err.max())
+
+
+def check_f16_sum(gpu: np.ndarray, ref: np.ndarray, scale: np.ndarray, what: str = ""):
+    """float16 storage of a float32 sum of unbounded size (gradients): the
+    float32 value lies within 1e-5 * sum |w v| of the exact one and is then
+    rounded once to float16, so |gpu - exact| <= half a float16 ulp at that
+    magnitude + the float32 bound."""
+    g = np.asarray(gpu).astype(np.float64)
+    err = np.abs(g - ref)
+    f32 = F32_REL * scale
+    mag = (np.abs(ref) + f32).astype(np.float16)
+    lim = 0.5 * np.spacing(mag).astype(np.float64) + f32 + 1e-30
+    worst = float((err / lim).max())
+    assert worst <= 1.0, f"{what}: float16 error {worst:.3g} x (half ulp + float32 bound)"
+    return worst
 
 
 def check_f32(gpu: np.ndarray, ref: np.ndarray, scale: np.ndarray, what: str = ""):

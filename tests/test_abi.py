@@ -138,6 +138,10 @@ def test_backward_validation():
     assert f(ctypes.byref(_img(32, 32, dtype=2, data=D2, row0=4, rows=8)), ctypes.byref(s), 0, None) == 6
     assert f(ctypes.byref(g), ctypes.byref(_img(16, 16, dtype=2, data=D2 + 64)), 0, None) == 7
     assert f(None, ctypes.byref(s), 0, None) == 1
+    # float16 gradients are accepted only in pairs; uint8 never
+    g16 = _img(32, 32, dtype=1, data=D2)
+    assert f(ctypes.byref(g16), ctypes.byref(s), 0, None) == 3
+    assert f(ctypes.byref(_img(32, 32, dtype=0, data=D2)), ctypes.byref(_img(16, 16, dtype=0)), 0, None) == 3
 
 
 def test_batch_validation():

@@ -5,7 +5,10 @@
   against the FP64 oracle adjoint, within 1e-5 * sum |w_y w_x g| per pixel;
 * the finite-difference Jacobian of the oracle forward on a 16 x 16 x 1 crop;
 * the 32 x 3 x 1024^2 -> 2048^2 float32 workload: forward rows, adjoint
-  planes, the adjoint identity <Ax, y> = <x, A^T y> and mass conservation.
+  planes, the adjoint identity <Ax, y> = <x, A^T y> and mass conservation;
+* float16 gradients (float32 sums, one rounding) on the same shapes, equal bit
+  for bit to the float32 result rounded to float16 wherever both run the
+  owner-computes kernel, and repeat runs bitwise identical (fixed order).
 """
 
 import numpy as np
@@ -18,7 +21,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1001_1718_amd as xr  # noqa: E402
-from gpu_util import check_f32, compare  # noqa: E402
+from gpu_util import check_f16_sum, check_f32, compare  # noqa: E402
 from oracle import ref_c  # noqa: E402
 from oracle import ref_resize as R  # noqa: E402
 from synth import fields  # noqa: E402
@@ -160,3 +163,79 @@ def test_adjoint_rejects_extreme_upscale():
     with pytest.raises(xr.XResizeError) as e:
         xr.resize_backward(g, (1, 4), "bicubic")
     assert e.value.code == 2
+
+
+def _is_up2(shape):
+    (in_h, in_w), (out_h, out_w) = shape
+    return out_h == 2 * in_h and out_w == 2 * in_w
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_adjoint_float16(shape, mode):
+    (in_h, in_w), (out_h, out_w) = shape
+    g16 = fields.normal_f32((2, 3, out_h, out_w), seed=out_h * 17 + out_w).astype(np.float16)
+    gd = torch.from_numpy(g16).to(DEV)
+    got = xr.resize_backward(gd, (in_h, in_w), mode)
+    assert got.dtype == torch.float16
+    again = xr.resize_backward(gd, (in_h, in_w), mode)
+    torch.cuda.synchronize()
+    got_np = got.cpu().numpy()
+    np.testing.assert_array_equal(again.cpu().numpy().view(np.uint16), got_np.view(np.uint16))
+    planes = g16.astype(np.float64).reshape(6, out_h, out_w, 1)
+    ref = R.adjoint(planes, in_h, in_w, MODES[mode]).reshape(2, 3, in_h, in_w)
+    scale = R.adjoint(planes, in_h, in_w, MODES[mode], absolute=True).reshape(2, 3, in_h, in_w)
+    check_f16_sum(got_np, ref, scale, what=f"adjoint f16 {shape} {mode}")
+    if not _is_up2(shape):  # same kernel and order in float32: one rounding apart
+        f32 = xr.resize_backward(gd.float(), (in_h, in_w), mode)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(f32.cpu().numpy().astype(np.float16).view(np.uint16),
+                                      got_np.view(np.uint16))
+
+
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_adjoint_float16_rgba_and_autograd(mode):
+    g16 = fields.normal_f32((2, 50, 70, 4), seed=21).astype(np.float16)
+    gs = xr.resize_backward(torch.from_numpy(g16).to(DEV), (33, 45), mode, layout="hwc")
+    torch.cuda.synchronize()
+    ref = R.adjoint(g16.astype(np.float64), 33, 45, MODES[mode])
+    scale = R.adjoint(g16.astype(np.float64), 33, 45, MODES[mode], absolute=True)
+    check_f16_sum(gs.cpu().numpy(), ref, scale, what=f"adjoint f16 rgba {mode}")
+    x = torch.from_numpy(fields.field_unit(24, 40, 3, seed=5, dtype=np.float16).transpose(2, 0, 1)[None].copy())
+    x = x.to(DEV).requires_grad_(True)
+    y = xr.ResizeFn.apply(x, (61, 29), mode)
+    g = torch.from_numpy(fields.normal_f32((1, 3, 61, 29), seed=8).astype(np.float16)).to(DEV)
+    y.backward(g)
+    torch.cuda.synchronize()
+    assert x.grad.dtype == torch.float16
+    gp = g.cpu().numpy().astype(np.float64).reshape(3, 61, 29, 1)
+    ref = R.adjoint(gp, 24, 40, MODES[mode]).reshape(1, 3, 24, 40)
+    scale = R.adjoint(gp, 24, 40, MODES[mode], absolute=True).reshape(1, 3, 24, 40)
+    check_f16_sum(x.grad.cpu().numpy(), ref, scale, what=f"autograd f16 {mode}")
+
+
+def test_adjoint_owner_is_deterministic_at_size():
+    """Non-x2 float32 adjoint over many tiles: two runs bitwise equal, and a
+    slice of the batch gives the same bits as the whole tensor."""
+    g = torch.from_numpy(fields.normal_f32((4, 3, 1500, 1100), seed=12)).to(DEV)
+    a = xr.resize_backward(g, (1024, 800), "bicubic")
+    b = xr.resize_backward(g, (1024, 800), "bicubic")
+    part = xr.resize_backward(g[1:3].contiguous(), (1024, 800), "bicubic")
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    assert torch.equal(a[1:3], part)
+    p = g[2, 1].cpu().numpy()[None, :, :, None]
+    ref = ref_c.adjoint(p, 1024, 800, 1)[0, :, :, 0]
+    scale = R.adjoint(p, 1024, 800, 1, absolute=True)[0, :, :, 0]
+    check_f32(a[2, 1].cpu().numpy(), ref, scale, what="owner adjoint at size")
+
+
+def test_adjoint_rejects_mixed_dtypes():
+    g = torch.zeros((1, 1, 8, 8), device=DEV, dtype=torch.float16)
+    out = torch.empty((1, 1, 4, 4), device=DEV, dtype=torch.float32)
+    with pytest.raises(xr.XResizeError) as e:
+        xr.resize_backward(g, (4, 4), "bilinear", out=out)
+    assert e.value.code == 3
+    with pytest.raises(xr.XResizeError) as e:
+        xr.resize_backward(torch.zeros((1, 1, 8, 8), device=DEV, dtype=torch.uint8), (4, 4), "bilinear")
+    assert e.value.code == 3
