@@ -73,23 +73,26 @@ __device__ __forceinline__ int32_t last_output(int32_t c, int32_t n_in, int32_t 
 
 // a.src = grad_dst (out_w x out_h), a.dst = grad_src (in_w x in_h), both
 // stored as T (float or _Float16), summed in float32.
-// Tile: tw columns x th rows of grad_src. LDS holds max_rows x tw x C floats
-// of u, max_rows x (K + 1) words of row taps, and per tile column the first
-// output column, the count and nmax weights of the outputs that reach it.
+// Tile: tw columns x th rows of grad_src (tw a power of two). LDS holds
+// max_rows x tw x C floats of u; per tile column the first output column, the
+// count and nmax weights of the outputs that reach it; per tile row the first
+// region row, the count and nmax_y weights of the output rows that reach it.
 template <int FILTER, typename T, int C>
 __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t tw, int32_t th,
-                                                           int32_t max_rows, int32_t nmax)
+                                                           int32_t max_rows, int32_t nmax, int32_t nmax_y)
 {
     using TP = Taps<FILTER>;
     constexpr int K = TP::K;
+    constexpr int RU = 8;  // region rows per thread and step of the horizontal pass
     extern __shared__ float lds[];
     const int32_t row_floats = tw * C;
-    float *u = lds;                                                           // [max_rows][tw*C]
-    int32_t *ylo = reinterpret_cast<int32_t *>(lds + max_rows * row_floats);  // [max_rows]
-    float *ywt = reinterpret_cast<float *>(ylo + max_rows);                   // [max_rows][K]
-    int32_t *colx = reinterpret_cast<int32_t *>(ywt + max_rows * K);          // [tw]
-    int32_t *coln = colx + tw;                                                // [tw]
-    float *colw = reinterpret_cast<float *>(coln + tw);                       // [tw][nmax]
+    float *u = lds;                                                             // [max_rows][tw*C]
+    int32_t *colx = reinterpret_cast<int32_t *>(u + max_rows * row_floats);    // [tw]
+    int32_t *coln = colx + tw;                                                  // [tw]
+    float *colw = reinterpret_cast<float *>(coln + tw);                         // [tw][nmax]
+    int32_t *rowk = reinterpret_cast<int32_t *>(colw + tw * nmax);              // [th]
+    int32_t *rown = rowk + th;                                                  // [th]
+    float *roww = reinterpret_cast<float *>(rown + th);                         // [th][nmax_y]
 
     const int32_t c_a = blockIdx.x * tw;
     const int32_t c_b = min(c_a + tw, a.in_w);
@@ -100,91 +103,109 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
     const int32_t yb = min(last_output<FILTER>(r_b - 1, a.in_h, a.out_h), ya + max_rows - 1);
     const int32_t nrows = yb - ya + 1;
     const int32_t ntc = c_b - c_a;
+    const int32_t ntr = r_b - r_a;
     const int32_t tid = threadIdx.x;
 
-    // phase 0: row taps of the region; per tile column c the outputs x whose
-    // clamped taps reach c (x in [first_output(c), last_output(c)], each with
-    // at least one tap on c) and the summed weight of those taps
-    for (int32_t k = tid; k < nrows; k += kBwdThreads) {
-        int32_t y0;
-        float t, omt;
-        axis_tap(ya + k, a.in_h, a.out_h, 1, y0, t, omt);
-        float w[K];
-        weights<FILTER>(t, omt, w);
-        ylo[k] = y0 + TP::LO;
-#pragma unroll
-        for (int j = 0; j < K; ++j)
-            ywt[k * K + j] = w[j];
-    }
-    for (int32_t cl = tid; cl < ntc; cl += kBwdThreads) {
-        const int32_t c = c_a + cl;
-        const int32_t xf = first_output<FILTER>(c, a.in_w, a.out_w);
-        const int32_t n = min(max(last_output<FILTER>(c, a.in_w, a.out_w) - xf + 1, 0), nmax);
-        colx[cl] = xf;
-        coln[cl] = n;
-        for (int32_t m = 0; m < n; ++m) {
+    // phase 0: for each tile column c (tile row r) the outputs whose clamped
+    // taps reach it, x in [first_output(c), last_output(c)], and the summed
+    // weight of those taps (taps ascending)
+    auto axis_table = [](int32_t c, int32_t n_in, int32_t n_out, int32_t nm, int32_t &first, int32_t &count,
+                         float *w) {
+        first = first_output<FILTER>(c, n_in, n_out);
+        count = min(max(last_output<FILTER>(c, n_in, n_out) - first + 1, 0), nm);
+        for (int32_t m = 0; m < count; ++m) {
             int32_t x0;
             float t, omt;
-            axis_tap(xf + m, a.in_w, a.out_w, 1, x0, t, omt);
-            float wx[K];
-            weights<FILTER>(t, omt, wx);
-            float w = 0.0f;
+            axis_tap(first + m, n_in, n_out, 1, x0, t, omt);
+            float wt[K];
+            weights<FILTER>(t, omt, wt);
+            float sum = 0.0f;
 #pragma unroll
             for (int i = 0; i < K; ++i)
-                if (clampi(x0 + TP::LO + i, 0, a.in_w - 1) == c)
-                    w += wx[i];
-            colw[cl * nmax + m] = w;
+                if (clampi(x0 + TP::LO + i, 0, n_in - 1) == c)
+                    sum += wt[i];
+            w[m] = sum;
+        }
+    };
+    for (int32_t t = tid; t < ntc + ntr; t += kBwdThreads) {
+        if (t < ntc) {
+            axis_table(c_a + t, a.in_w, a.out_w, nmax, colx[t], coln[t], colw + t * nmax);
+        } else {
+            const int32_t i = t - ntc;
+            int32_t yf, n;
+            axis_table(r_a + i, a.in_h, a.out_h, nmax_y, yf, n, roww + i * nmax_y);
+            // first_output and last_output are monotone, so the rows lie in
+            // the region ya .. yb (yf >= ya; the min only guards the LDS)
+            rowk[i] = yf - ya;
+            rown[i] = max(min(n, nrows - (yf - ya)), 0);
         }
     }
     __syncthreads();
 
-    // phase 1: horizontal adjoint as a gather, one (region row, tile column)
-    // per thread: u[k][c] = sum over x ascending of w(x, c) g[ya + k][x]
+    // phase 1: horizontal adjoint as a gather: u[k][c] = sum over x ascending
+    // of w(x, c) g[ya + k][x]. A thread owns one tile column and RU region
+    // rows per step, so RU loads are in flight per weight.
     const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
-    for (int32_t item = tid; item < nrows * ntc; item += kBwdThreads) {
-        const int32_t k = item / ntc, cl = item - k * ntc;
-        const unsigned char *grow = gsrc + static_cast<int64_t>(ya + k) * a.src_pitch;
+    const int32_t phases = kBwdThreads / tw;
+    const int32_t cl = tid & (tw - 1), kq = tid / tw;
+    if (cl < ntc) {
         const int32_t xf = colx[cl], n = coln[cl];
         const float *w = colw + cl * nmax;
-        float acc[C], g[C];
-        if (n > 0) {
-            Pix<T, C>::load(grow, xf, g);
-            fma_first(acc, w[0], g);
-            for (int32_t m = 1; m < n; ++m) {
-                Pix<T, C>::load(grow, xf + m, g);
-                fma_next(acc, w[m], g);
+        for (int32_t k0 = kq * RU; k0 < nrows; k0 += phases * RU) {
+            const unsigned char *grow[RU];
+#pragma unroll
+            for (int q = 0; q < RU; ++q)
+                grow[q] = gsrc + static_cast<int64_t>(ya + min(k0 + q, nrows - 1)) * a.src_pitch;
+            float acc[RU][C];
+            if (n > 0) {
+                const float w0 = w[0];
+#pragma unroll
+                for (int q = 0; q < RU; ++q) {
+                    float g[C];
+                    Pix<T, C>::load(grow[q], xf, g);
+                    fma_first(acc[q], w0, g);
+                }
+                for (int32_t m = 1; m < n; ++m) {
+                    const float wm = w[m];
+#pragma unroll
+                    for (int q = 0; q < RU; ++q) {
+                        float g[C];
+                        Pix<T, C>::load(grow[q], xf + m, g);
+                        fma_next(acc[q], wm, g);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < RU; ++q)
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch)
+                        acc[q][ch] = 0.0f;
             }
-        } else {
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                acc[ch] = 0.0f;
+            for (int q = 0; q < RU; ++q)
+                if (k0 + q < nrows) {
+                    float *urow = u + (k0 + q) * row_floats + cl * C;
+#pragma unroll
+                    for (int ch = 0; ch < C; ++ch)
+                        urow[ch] = acc[q][ch];
+                }
         }
-        float *urow = u + k * row_floats + cl * C;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            urow[ch] = acc[ch];
     }
     __syncthreads();
 
-    // phase 2: vertical adjoint, one (column, channel) per thread
+    // phase 2: vertical adjoint, one (column, channel) per thread:
+    // grad[r][c] = sum over region rows k ascending of w(y, r) u[k][c]
     unsigned char *gdst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
     const int32_t ncols = ntc * C;
     for (int32_t f = tid; f < ncols; f += kBwdThreads) {
-        int32_t k_first = 0;  // first region row whose taps reach the current r
-        for (int32_t r = r_a; r < r_b; ++r) {
-            while (k_first < nrows && clampi(ylo[k_first] + K - 1, 0, a.in_h - 1) < r)
-                ++k_first;
+        for (int32_t i = 0; i < ntr; ++i) {
+            const int32_t k0 = rowk[i], n = rown[i];
+            const float *wr = roww + i * nmax_y;
             float acc = 0.0f;
-            for (int32_t k = k_first; k < nrows && clampi(ylo[k], 0, a.in_h - 1) <= r; ++k) {
-                float w = 0.0f;
-#pragma unroll
-                for (int j = 0; j < K; ++j)
-                    if (clampi(ylo[k] + j, 0, a.in_h - 1) == r)
-                        w += ywt[k * K + j];
-                acc = __builtin_fmaf(w, u[k * row_floats + f], acc);
-            }
+            for (int32_t j = 0; j < n; ++j)
+                acc = __builtin_fmaf(wr[j], u[(k0 + j) * row_floats + f], acc);
             const float v[1] = {acc};
-            Pix<T, 1>::store(gdst + static_cast<int64_t>(r) * a.dst_pitch, c_a * C + f, v);
+            Pix<T, 1>::store(gdst + static_cast<int64_t>(r_a + i) * a.dst_pitch, c_a * C + f, v);
         }
     }
 }
@@ -432,7 +453,7 @@ hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
 // across the threads) and th source rows, shrunk until the region of output
 // rows and the column tables fit the LDS budget.
 struct BwdPlan {
-    int32_t tw, th, max_rows, nmax;
+    int32_t tw, th, max_rows, nmax, nmax_y;
     size_t lds;
 };
 
@@ -443,17 +464,19 @@ BwdPlan plan_backward(const ResizeArgs &a)
     constexpr size_t kBudget = 64 * 1024;
     BwdPlan p{};
     // outputs reaching one source column: at most ceil(K out / in) + 1 inside,
-    // (1 - LO + 1/2) out / in + 1 at a clamped border
+    // (1 - LO + 1/2) out / in + 1 at a clamped border; rows alike
     p.nmax = static_cast<int32_t>((static_cast<int64_t>(K) * a.out_w + a.in_w - 1) / a.in_w + 2);
+    p.nmax_y = static_cast<int32_t>((static_cast<int64_t>(K) * a.out_h + a.in_h - 1) / a.in_h + 2);
     p.tw = kBwdThreads / C;
     p.th = 16;
     for (;;) {
         // output rows touching th source rows: at most (th + K - 1) * out/in + 2
         const int64_t rows = (static_cast<int64_t>(p.th + K - 1) * a.out_h + a.in_h - 1) / a.in_h + 2;
         p.max_rows = static_cast<int32_t>(rows);
-        p.lds = static_cast<size_t>(rows) * (p.tw * C * sizeof(float) + (K + 1) * sizeof(int32_t)) +
-                static_cast<size_t>(p.tw) * (2 + static_cast<size_t>(p.nmax)) * sizeof(float);
-        if (p.lds <= kBudget)
+        p.lds = sizeof(float) * (static_cast<size_t>(rows) * p.tw * C +
+                                 static_cast<size_t>(p.tw) * (2 + static_cast<size_t>(p.nmax)) +
+                                 static_cast<size_t>(p.th) * (2 + static_cast<size_t>(p.nmax_y)));
+        if (rows < (int64_t{1} << 24) && p.lds <= kBudget)
             return p;
         if (p.th > 1) {
             p.th /= 2;
@@ -478,7 +501,7 @@ hipError_t launch_bwd_typed(const ResizeArgs &a, hipStream_t stream)
         return hipErrorInvalidConfiguration;
     const dim3 grid((a.in_w + p.tw - 1) / p.tw, (a.in_h + p.th - 1) / p.th, a.planes);
     hipLaunchKernelGGL((k_bwd_owner<FILTER, T, C>), grid, dim3(kBwdThreads), p.lds, stream, a, p.tw, p.th,
-                       p.max_rows, p.nmax);
+                       p.max_rows, p.nmax, p.nmax_y);
     return hipGetLastError();
 }
 
