@@ -16,7 +16,9 @@ Printed JSON line (one):
               (profiles/pmc_*.txt), or null if those were taken on other kernel
               sources
   cpu_baseline the FP64 C oracle on a bounded sample of output rows, timed on
-              the host cores
+              all host cores (the value) and on one thread, with the host's
+              CPU model; the batched comparison and every extra row carry the
+              oracle's rate on a sample of the same workload
   batched     256 uneven uint8 images: one persistent launch replayed from a
               HIP graph vs 256 per-image launches (eager and graph-captured),
               images/s, outputs bitwise identical across the three
@@ -189,43 +191,124 @@ def hbm_reference(torch, reps: int = 20):
     return res
 
 
-def cpu_baseline(src_host, target_s: float = 10.0):
+def host_cpu() -> dict:
+    """The host's CPU model and core count (for the oracle timings)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def cpu_baseline_sample(planes, out_h: int, out_w: int, mode: str, target_s: float, threads: int = 0,
+                        mapping: str = "half_pixel"):
+    """The oracle on evenly spaced output rows of one workload, sized to about
+    target_s seconds: returns (output pixels per second, rows, passes, threads).
+
+    planes: host array (P, H, W, C); the rate counts output pixels of one plane
+    (H x W x C values make one pixel when C is interleaved). Bilinear and
+    bicubic with pixel centres run the C oracle (OpenMP, `threads` = 0: all);
+    the other filters and maps run the numpy oracle (one thread)."""
     from oracle import ref_c
+    from oracle import ref_resize as R
     from oracle.build import LIBRARY, build_oracle
     import numpy as np
 
-    if not os.path.exists(LIBRARY):
+    codes = {"bilinear": 0, "bicubic": 1, "nearest": 2, "bilinear_aa": 3, "bicubic_aa": 4}
+    filt = codes[mode]
+    use_c = filt in (0, 1) and mapping == "half_pixel"
+    if use_c and not os.path.exists(LIBRARY):
         build_oracle()
-    out_hw = 8192
-    threads = ref_c.max_threads()
+    used = (ref_c.max_threads() if threads == 0 else threads) if use_c else 1
+    if use_c:  # the C oracle reads float32 planes: convert (exactly) once, outside the timing
+        planes = np.ascontiguousarray(np.asarray(planes).astype(np.float32))
 
     def run(n_rows):
-        rows = np.linspace(0, out_hw - 1, n_rows).astype(np.int64)
+        rows = np.linspace(0, out_h - 1, n_rows).astype(np.int64)
         t0 = time.perf_counter()
-        ref_c.resize_rows(src_host, out_hw, out_hw, rows, 1)
+        if use_c:
+            ref_c.resize_rows(planes, out_h, out_w, rows, filt, threads=threads)
+        elif filt in (3, 4):
+            R.resize_antialiased(planes, out_h, out_w, filt, rows=rows)
+        else:
+            R.resize_rows(planes, out_h, out_w, rows, filt, mapping=1 if mapping == "paper" else 0)
         return time.perf_counter() - t0
 
-    probe_rows = 16
-    t = run(probe_rows)
-    n_rows = int(min(out_hw, max(probe_rows, probe_rows * target_s / max(t, 1e-6))))
-    if n_rows < out_hw:
-        passes = 1
+    probe = min(4, out_h)
+    t = run(probe)
+    n_rows = int(min(out_h, max(probe, probe * target_s / max(t, 1e-6))))
+    passes = 1
+    if n_rows < out_h:
         t = run(n_rows)
     else:
-        # the whole image takes less than the target: repeat whole passes
-        t1 = run(out_hw)
+        t1 = run(out_h)
         passes = max(1, int(target_s / max(t1, 1e-6)))
-        t = t1 + sum(run(out_hw) for _ in range(passes - 1))
-    px = n_rows * out_hw * passes
+        t = t1 + sum(run(out_h) for _ in range(passes - 1))
+    px = n_rows * out_w * passes * planes.shape[0]
+    return px / t, n_rows, passes, used, t
+
+
+def cpu_baseline_adjoint(grad, in_h: int, in_w: int, mode: str):
+    """The oracle adjoint (FP64 C, OpenMP over planes) of as many whole planes
+    of the NCHW gradient tensor `grad` as it has threads: gradient pixels per
+    second, the cores used and the seconds taken."""
+    from oracle import ref_c
+    from oracle.build import LIBRARY, build_oracle
+
+    if not os.path.exists(LIBRARY):
+        build_oracle()
+    k = min(ref_c.max_threads(), grad.shape[0] * grad.shape[1])
+    grad_planes = grad.reshape(-1, grad.shape[-2], grad.shape[-1])[:k].float().cpu().numpy()[..., None]
+    t0 = time.perf_counter()
+    ref_c.adjoint(grad_planes, in_h, in_w, 1 if mode == "bicubic" else 0)
+    t = time.perf_counter() - t0
+    return grad_planes.shape[0] * in_h * in_w / t, min(ref_c.max_threads(), grad_planes.shape[0]), t
+
+
+def cpu_baseline_batch(jobs, srcs_host, rows_per_image: int = 2):
+    """The oracle on `rows_per_image` evenly spaced output rows of every image
+    of a batch, extrapolated to the whole batch: images per second."""
+    import numpy as np
+
+    from oracle import ref_c
+
+    total = 0.0
+    for j, host in zip(jobs, srcs_host):
+        planes = np.ascontiguousarray(host[None].astype(np.float32))  # widened outside the timing
+        mode = "bicubic" if j.filter == 1 else "bilinear"
+        n = min(rows_per_image, j.out_h)
+        rows = np.linspace(0, j.out_h - 1, n).astype(np.int64)
+        t0 = time.perf_counter()
+        ref_c.resize_rows(planes, j.out_h, j.out_w, rows, 1 if mode == "bicubic" else 0)
+        total += (time.perf_counter() - t0) * j.out_h / n
+    return len(jobs) / total
+
+
+def cpu_baseline(src_host, target_s: float = 10.0):
+    """The FP64 C oracle on the headline workload: all host cores (the
+    reported value), then one thread on a smaller sample."""
+    planes = src_host[None]
+    rate, n_rows, passes, used, t = cpu_baseline_sample(planes, 8192, 8192, "bicubic", target_s)
+    rate1, rows1, _, _, t1 = cpu_baseline_sample(planes, 8192, 8192, "bicubic", target_s / 4, threads=1)
+    px = n_rows * 8192 * passes
     what = (f"{n_rows} evenly spaced output rows" if passes == 1 else
             f"the whole 8192 x 8192 output, {passes} passes")
-    return {"value": round(px / t / 1e9, 6), "unit": "Gpixel/s", "cores": threads, "kind": "oracle",
+    return {"value": round(rate / 1e9, 6), "unit": "Gpixel/s", "cores": used, "kind": "oracle",
             "seconds": round(t, 2),
             "sample": f"{what} of the bicubic x2 4096x4096 RGBA uint8 workload "
-                      f"({px / 1e6:.1f} Mpx), FP64 C oracle, OpenMP"}
+                      f"({px / 1e6:.1f} Mpx), FP64 C oracle, OpenMP, input widened to float32 "
+                      f"before timing",
+            "one_thread": {"value": round(rate1 / 1e9, 6), "unit": "Gpixel/s", "seconds": round(t1, 2),
+                           "sample": f"{rows1} evenly spaced output rows"},
+            **host_cpu()}
 
 
-def batched(torch, xr, fields, reps: int = 5):
+def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
     dev = torch.device("cuda:0")
     jobs = fields.batch_jobs(0)
     log("generating the 256-image uneven batch (sides 64..2048, scales 0.25..4)")
@@ -299,7 +382,14 @@ def batched(torch, xr, fields, reps: int = 5):
     wall = time.perf_counter() - t0
     res["persistent_graph"] = len(pairs) * reps / wall
     launch_ms = ev0.elapsed_time(ev1) / reps
+    cpu_res = {}
+    if cpu:
+        log("timing the oracle on 2 rows of every image (extrapolated)")
+        ips = cpu_baseline_batch(jobs, [s.cpu().numpy() for s, _, _ in pairs])
+        cpu_res = {"cpu_images_per_s": round(ips, 3), "cpu_sample": "2 evenly spaced output rows per image, "
+                   "extrapolated to whole images (FP64 C oracle, all host cores)"}
     return {
+        **cpu_res,
         "workload": "256 uint8 images (1 or 4 ch), sides U{64..2048}, per-axis scale U(0.25, 4), "
                     "128 bilinear + 128 bicubic, smooth-field content, seed 0",
         "images_per_s": {k: round(v, 1) for k, v in res.items()},
@@ -313,10 +403,25 @@ def batched(torch, xr, fields, reps: int = 5):
     }
 
 
-def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
-    """Gpixel/s and GB/s of the other storage types and workloads."""
+def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True):
+    """Gpixel/s and GB/s of the other storage types and workloads, each with
+    the oracle's rate on a sample of the same workload (about 1 s of host time;
+    `cpu_mpx_s`, the cores it used and its sample) unless cpu is False."""
     dev = torch.device("cuda:0")
     out = {}
+
+    def oracle_rate(src, out_hw, mode, layout, mapping="half_pixel"):
+        if not cpu:
+            return {}
+        host = src.cpu().numpy()
+        if layout == "hwc":
+            planes = host[None] if host.ndim == 3 else host[None, :, :, None]
+        else:  # planar: one plane stands for all
+            planes = host.reshape(-1, host.shape[-2], host.shape[-1], 1)[:1]
+        rate, n_rows, passes, used, _ = cpu_baseline_sample(planes, out_hw[0], out_hw[1], mode, 1.0,
+                                                            mapping=mapping)
+        return {"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
+                "cpu_sample": f"{n_rows} rows x {passes} passes" if passes > 1 else f"{n_rows} rows"}
 
     def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel"):
         src0 = make_src()
@@ -346,7 +451,8 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
         out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
                      "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
-                     "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+                     "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4),
+                     **oracle_rate(src0, out_hw, mode, layout, mapping)}
         log(f"extra {name}: {out[name]}")
         del srcs, dsts
         torch.cuda.empty_cache()
@@ -380,7 +486,12 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
         k_s = sum(ms) / len(ms) / 1e3
         alg = (g.numel() + gs.numel()) * g.element_size()
         out[name] = {"ms": round(k_s * 1e3, 4), "gbs": round(alg / k_s / 1e9, 1),
-                     "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4)}
+                     "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4),
+                     "gpixel_s": round(gs.numel() / k_s / 1e9, 2)}
+        if cpu:
+            rate, used, t = cpu_baseline_adjoint(g, in_hw[0], in_hw[1], mode)
+            out[name].update({"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
+                              "cpu_sample": f"{used} whole planes"})
         log(f"extra {name}: {out[name]}")
         del g, gs
         torch.cuda.empty_cache()
@@ -412,7 +523,8 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5):
     out["c5_bicubic_x2_f16_16384"] = {"whole_ms": round(whole * 1e3, 3), "bands16_ms": round(bands * 1e3, 3),
                                       "gbs": round(alg / whole / 1e9, 1),
                                       "hbm_frac": round(alg / whole / 1e9 / HBM_PEAK_GBS, 4),
-                                      "bands_bitwise_equal": bool(torch.equal(dst, dst_b))}
+                                      "bands_bitwise_equal": bool(torch.equal(dst, dst_b)),
+                                      **oracle_rate(src, (32768, 32768), "bicubic", "hwc")}
     log(f"extra C5: {out['c5_bicubic_x2_f16_16384']}")
     return out
 
@@ -526,12 +638,12 @@ def main():
     }
     result["hbm_reference"] = hbm_reference(torch)
     if not args.no_batch:
-        result["batched"] = batched(torch, xr, fields)
+        result["batched"] = batched(torch, xr, fields, cpu=not args.no_cpu)
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(h["src_host"])
     if args.extras:
-        result["extras"] = extras(torch, xr, fields)
+        result["extras"] = extras(torch, xr, fields, cpu=not args.no_cpu)
     print(json.dumps(result), flush=True)
 
 

@@ -90,14 +90,16 @@ int oracle_resize_rows(const float *src, int64_t planes, int64_t in_h, int64_t i
     for (int64_t r = 0; r < nrows; ++r)
         if (rows[r] < 0 || rows[r] >= out_h)
             return -1;
+    /* the thread count applies to this call only (num_threads clause) */
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
+    const int nt = 1;
     (void)nthreads;
 #endif
+    (void)nt;
     int64_t total = planes * nrows;
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int64_t pr = 0; pr < total; ++pr) {
         int64_t p = pr / nrows;
         int64_t r = pr % nrows;
@@ -133,13 +135,15 @@ int oracle_adjoint(const float *grad_out, int64_t planes, int64_t out_h, int64_t
     if (!grad_out || !grad_src || planes < 1 || in_h < 1 || in_w < 1 || ch < 1 || out_h < 1 ||
         out_w < 1 || (filt != ORACLE_BILINEAR && filt != ORACLE_BICUBIC))
         return -1;
+    /* the thread count applies to this call only (num_threads clause) */
 #ifdef _OPENMP
-    if (nthreads > 0)
-        omp_set_num_threads(nthreads);
+    const int nt = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
+    const int nt = 1;
     (void)nthreads;
 #endif
-#pragma omp parallel for schedule(dynamic, 1)
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int64_t p = 0; p < planes; ++p) {
         double *gs = grad_src + p * in_h * in_w * ch;
         const float *g = grad_out + p * out_h * out_w * ch;
