@@ -62,6 +62,34 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def read_valu(name: str, tile, kernel_s: float):
+    """VALU issue time per launch from a committed instruction-counter summary
+    (SQ_INSTS_VALU x cycles per instruction / SIMDs / clock), when it was taken
+    on these kernel sources and this launch shape; else None."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals.get("kernel_sources_sha256_16") != kernel_hash():
+            return None
+        want = [int(x) for x in vals["tile"].split(",")]
+        have = [tile.kernel, tile.block_w, tile.block_h, tile.ppt_x, tile.ppt_y, tile.order]
+        if want != have:
+            return None
+        insts = int(vals["SQ_INSTS_VALU"])
+        issue_s = insts * int(vals["cycles_per_valu_inst"]) / int(vals["simds"]) / (float(vals["clock_ghz"]) * 1e9)
+        return {"valu_insts_per_launch": insts, "issue_us": round(issue_s * 1e6, 1),
+                "issue_frac": round(issue_s / kernel_s, 3)}
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
 def read_pmc(name: str):
     """HBM traffic per launch from a committed rocprofv3 counter summary."""
     path = os.path.join(ROOT, "profiles", name)
@@ -154,7 +182,9 @@ def headline(args, torch, xr, fields):
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
                 "alg_bytes_per_launch": alg, "kernel_ms": {k: round(v, 5) for k, v in stats.items()},
-                "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2)}
+                "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2),
+                # the FP32 VALU check: instruction issue time from the counters
+                "valu": read_valu("sq_k_strip_up2_bicubic_x2_u8rgba.txt", resolved, kernel_s)}
     return {
         "value": value, "wall": wall, "roofline": roofline, "tile": repr(resolved), "tune": tune,
         "n_buf": n_buf, "src_host": srcs[0].cpu().numpy(),
