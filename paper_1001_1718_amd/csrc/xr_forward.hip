@@ -362,11 +362,24 @@ __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int3
     const int32_t wy0 = ylo[0];
     const int32_t wh = min(ylo[bh - 1] + yn[bh - 1] - wy0, win_h);
     const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
-    for (int32_t i = tid; i < ww * wh; i += nthreads) {
-        const int32_t r = i / ww, c = i - r * ww;
-        const unsigned char *row = src + static_cast<int64_t>(wy0 + r - a.src_row0) * a.src_pitch;
-        copy_pixel<PB>(win + (static_cast<int64_t>(r) * win_w + c) * PB,
-                       row + static_cast<int64_t>(wx0 + c) * PB);
+    // NB loads in flight per thread before any LDS store
+    constexpr int NB = 8;
+    const int32_t total = ww * wh;
+    for (int32_t base = 0; base < total; base += nthreads * NB) {
+        RawBuf<PB, PB> v[NB];
+        int32_t off[NB];
+#pragma unroll
+        for (int k = 0; k < NB; ++k) {
+            const int32_t i = min(base + tid + k * nthreads, total - 1);
+            const int32_t r = i / ww, c = i - r * ww;
+            off[k] = (r * win_w + c) * PB;
+            v[k] = load_raw<PB, PB>(src + static_cast<int64_t>(wy0 + r - a.src_row0) * a.src_pitch +
+                                    static_cast<int64_t>(wx0 + c) * PB);
+        }
+#pragma unroll
+        for (int k = 0; k < NB; ++k)
+            if (base + tid + k * nthreads < total)
+                store_raw<PB, PB>(win + off[k], v[k]);
     }
     __syncthreads();
     // horizontal pass: window row r, tile column c
