@@ -362,32 +362,45 @@ __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int3
     const int32_t wy0 = ylo[0];
     const int32_t wh = min(ylo[bh - 1] + yn[bh - 1] - wy0, win_h);
     const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
-    // NB loads in flight per thread before any LDS store
+    // NB loads in flight per thread before any LDS store. Element i of the
+    // window is (i / ww, i % ww); a thread's elements step by nthreads, i.e.
+    // by dr rows and dc columns with a carry, so no division per element.
     constexpr int NB = 8;
     const int32_t total = ww * wh;
-    for (int32_t base = 0; base < total; base += nthreads * NB) {
+    const int32_t dr = nthreads / ww, dc = nthreads - dr * ww;
+    int32_t r = tid / ww, c = tid - (tid / ww) * ww;
+    const unsigned char *wsrc = src + static_cast<int64_t>(wy0 - a.src_row0) * a.src_pitch +
+                                static_cast<int64_t>(wx0) * PB;
+    for (int32_t base = tid; base < total; base += nthreads * NB) {
         RawBuf<PB, PB> v[NB];
         int32_t off[NB];
 #pragma unroll
         for (int k = 0; k < NB; ++k) {
-            const int32_t i = min(base + tid + k * nthreads, total - 1);
-            const int32_t r = i / ww, c = i - r * ww;
-            off[k] = (r * win_w + c) * PB;
-            v[k] = load_raw<PB, PB>(src + static_cast<int64_t>(wy0 + r - a.src_row0) * a.src_pitch +
-                                    static_cast<int64_t>(wx0 + c) * PB);
+            // past the end: reload the window's last element (a valid address)
+            const bool in = base + k * nthreads < total;
+            const int32_t rr = in ? r : wh - 1, cc = in ? c : ww - 1;
+            off[k] = (rr * win_w + cc) * PB;
+            v[k] = load_raw<PB, PB>(wsrc + static_cast<int64_t>(rr) * a.src_pitch + cc * PB);
+            c += dc;
+            r += dr + (c >= ww ? 1 : 0);
+            c -= c >= ww ? ww : 0;
         }
 #pragma unroll
         for (int k = 0; k < NB; ++k)
-            if (base + tid + k * nthreads < total)
+            if (base + k * nthreads < total)
                 store_raw<PB, PB>(win + off[k], v[k]);
     }
     __syncthreads();
-    // horizontal pass: window row r, tile column c
-    for (int32_t i = tid; i < wh * bw; i += nthreads) {
-        const int32_t r = i / bw, c = i - r * bw;
+    // horizontal pass: window row r, tile column c (threads of one column
+    // take rows ty, ty + bh, ...)
+    const int32_t hc = threadIdx.x;
+    const int32_t hx0 = xlo[hc] - wx0, hnx = xn[hc];
+    const float *hwx = xw + hc * kx;
+    for (int32_t r = threadIdx.y; r < wh; r += bh) {
+        const int32_t c = hc;
         const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
-        const int32_t x0 = xlo[c] - wx0, nx = xn[c];
-        const float *wxr = xw + c * kx;
+        const int32_t x0 = hx0, nx = hnx;
+        const float *wxr = hwx;
         float h[C], p[C];
         Pix<T, C>::load(wrow, x0, p);
         fma_first(h, wxr[0], p);
