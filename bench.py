@@ -453,11 +453,14 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         return {"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
                 "cpu_sample": f"{n_rows} rows x {passes} passes" if passes > 1 else f"{n_rows} rows"}
 
-    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel"):
+    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel",
+                rotate=True):
         src0 = make_src()
         in_bytes = src0.numel() * src0.element_size()
         out_bytes = math.prod(out_shape) * src0.element_size()
-        n_buf = max(1, math.ceil(ROTATE_BYTES / (in_bytes + out_bytes)))
+        # rotate over >= 1 GiB of buffers so the 256 MB Infinity Cache cannot
+        # hold the working set between launches (unless rotate is False)
+        n_buf = max(1, math.ceil(ROTATE_BYTES / (in_bytes + out_bytes))) if rotate else 1
         srcs = [src0] + [src0.clone() for _ in range(n_buf - 1)]
         dsts = [torch.empty(out_shape, dtype=src0.dtype, device=dev) for _ in range(n_buf)]
 
@@ -480,6 +483,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         # pixels: H * W for interleaved images, N * C * H * W for planar tensors
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
         out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
+                     "buffers": n_buf,
                      "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
                      "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4),
                      **oracle_rate(src0, out_hw, mode, layout, mapping)}
@@ -501,6 +505,9 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
     del fld, unit, u8
     measure("c1_bilinear_x2_u8_512", lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev),
             (1024, 1024), "bilinear")
+    measure("c1_bilinear_x2_u8_512_unrotated",
+            lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev), (1024, 1024), "bilinear",
+            rotate=False)
     measure("c4_bilinear_x2_f32_nchw_fwd", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
             (32, 3, 2048, 2048), "bilinear", layout="nchw")
     # C4 adjoint (exact x2 float32: register walk), and the owner-computes
@@ -607,8 +614,10 @@ def paper_sweep(torch, xr, fields, reps: int = 10, groups: int = 3):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    # 10 groups of 100 timed launches (each group's mean per launch; the
+    # median and range over groups are reported)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")

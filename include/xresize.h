@@ -256,8 +256,9 @@ int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candida
  * contributions of every output pixel that touches the tile (rows of the
  * horizontal adjoint in LDS, then columns) and stores the tile once: no
  * atomics, no clearing pass. Every sum runs in a fixed order, so the result
- * is deterministic. Exact x2 in float32 takes a register walk plus a border
- * pass instead (also deterministic). XR_ERR_SHAPE if the upscale is too
+ * is deterministic. Exact x2 takes a register walk plus a border pass
+ * instead (also deterministic; with float16 storage the border pixels are
+ * summed in full there, so every gradient is rounded once). XR_ERR_SHAPE if the upscale is too
  * strong for one tile (rows beyond about 190x, columns beyond a few hundred x).
  */
 int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32_t filter,

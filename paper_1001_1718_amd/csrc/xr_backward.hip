@@ -34,11 +34,16 @@ namespace {
 
 constexpr int kBwdThreads = 256;
 
-// N bytes of float32 data moved as one aligned vector access
-template <int N>
-struct alignas(16) RawBytes {
-    float f[N / 4];
+// N values of T moved as one aligned vector access (ALIGN bytes)
+template <typename T, int N, int ALIGN>
+struct alignas(ALIGN) RawVals {
+    T v[N];
 };
+
+// Alignment of the x2 walk's row runs: they start at (2 c0 + SX0) C sizeof(T)
+// bytes, a multiple of 16 for float32 and of 8 for float16.
+template <typename T>
+constexpr int kRunAlign = sizeof(T) == 4 ? 16 : 8;
 
 // First output index whose clamped taps reach source index >= c, for the
 // axis n_in -> n_out (the map is monotone; see eqs. 1-4).
@@ -233,13 +238,13 @@ struct BwdUp2 {
     static constexpr int Q = 2;                        // output rows per step
 };
 
-template <int FILTER, int C, int P>
+template <int FILTER, typename T, int C, int P>
 __global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
 {
     using B = BwdUp2<FILTER, C, P>;
     constexpr int K = B::K;
     constexpr int SX = B::SX;
-    static_assert(C == 4 || P == 4, "float32 rows are read 16 pixels at a time");
+    static_assert(C == 4 || P == 4, "one-channel rows are read 16 pixels at a time");
     float we[K], wo[K];
     weights<FILTER>(0.75f, 0.25f, we);
     weights<FILTER>(0.25f, 0.75f, wo);
@@ -266,20 +271,20 @@ __global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
         const int32_t yy = clampi(y, 0, a.out_h - 1);
         const unsigned char *row = gsrc + static_cast<int64_t>(yy) * a.src_pitch;
         if (wide) {
-            const auto raw = *reinterpret_cast<const RawBytes<SX * C * 4> *>(
-                __builtin_assume_aligned(row + static_cast<int64_t>(xs) * C * 4, 16));
+            const auto raw = *reinterpret_cast<const RawVals<T, SX * C, kRunAlign<T>> *>(
+                __builtin_assume_aligned(row + static_cast<int64_t>(xs) * C * sizeof(T), kRunAlign<T>));
 #pragma unroll
             for (int s = 0; s < SX; ++s)
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)
-                    v[s][ch] = row_ok ? raw.f[s * C + ch] : 0.0f;
+                    v[s][ch] = row_ok ? static_cast<float>(raw.v[s * C + ch]) : 0.0f;
         } else {
 #pragma unroll
             for (int s = 0; s < SX; ++s) {
                 const int32_t x = xs + s;
                 const bool ok = row_ok && x >= 0 && x < a.out_w;
                 float p[C];
-                Pix<float, C>::load(row, clampi(x, 0, a.out_w - 1), p);
+                Pix<T, C>::load(row, clampi(x, 0, a.out_w - 1), p);
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)
                     v[s][ch] = ok ? p[ch] : 0.0f;
@@ -327,19 +332,19 @@ __global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
         }
         unsigned char *drow = gdst + static_cast<int64_t>(r) * a.dst_pitch;
         if (wide) {
-            RawBytes<P * C * 4> out;
+            RawVals<T, P * C, kRunAlign<T>> out;
 #pragma unroll
             for (int p = 0; p < P; ++p)
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)
-                    out.f[p * C + ch] = g[p][ch];
-            *reinterpret_cast<RawBytes<P * C * 4> *>(
-                __builtin_assume_aligned(drow + static_cast<int64_t>(c0) * C * 4, 16)) = out;
+                    out.v[p * C + ch] = static_cast<T>(g[p][ch]);
+            *reinterpret_cast<RawVals<T, P * C, kRunAlign<T>> *>(
+                __builtin_assume_aligned(drow + static_cast<int64_t>(c0) * C * sizeof(T), kRunAlign<T>)) = out;
         } else {
 #pragma unroll
             for (int p = 0; p < P; ++p)
                 if (p < ncols)
-                    Pix<float, C>::store(drow, c0 + p, g[p]);
+                    Pix<T, C>::store(drow, c0 + p, g[p]);
         }
     };
     // the window of row r starts at slot (2(r - r_a)) mod 2K; unroll K rows so
@@ -360,10 +365,13 @@ __global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
 // Border source pixels: add the terms whose row or column tap was clamped onto
 // them (the interior walk above left those out). One thread per border pixel
 // and plane; index k walks row 0, row in_h-1, then columns 0 and in_w-1 of
-// the rows in between.
-template <int FILTER, int C>
+// the rows in between. With float16 storage the walk's value is already
+// rounded, so the border pixels are summed here in full (every term) and
+// overwritten: each gradient is rounded once.
+template <int FILTER, typename T, int C>
 __global__ void __launch_bounds__(256) k_bwd_up2_border(ResizeArgs a)
 {
+    constexpr bool kFull = !std::is_same_v<T, float>;
     using TP = Taps<FILTER>;
     constexpr int K = TP::K;
     const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,39 +420,44 @@ __global__ void __launch_bounds__(256) k_bwd_up2_border(ResizeArgs a)
 #pragma unroll
                 for (int i = 0; i < K; ++i) {
                     const int32_t cx = x0 + TP::LO + i;
-                    if (clampi(cx, 0, a.in_w - 1) == c && (ry != r || cx != c))
+                    if (clampi(cx, 0, a.in_w - 1) == c && (kFull || ry != r || cx != c))
                         w += wy[j] * wx[i];
                 }
             }
             if (w != 0.0f) {
                 float g[C];
-                Pix<float, C>::load(grow, x, g);
+                Pix<T, C>::load(grow, x, g);
 #pragma unroll
                 for (int ch = 0; ch < C; ++ch)
                     extra[ch] = __builtin_fmaf(w, g[ch], extra[ch]);
             }
         }
     }
-    float *out = reinterpret_cast<float *>(a.dst + static_cast<int64_t>(blockIdx.y) * a.dst_plane_pitch +
-                                           static_cast<int64_t>(r) * a.dst_pitch) + c * C;
+    unsigned char *orow = a.dst + static_cast<int64_t>(blockIdx.y) * a.dst_plane_pitch +
+                          static_cast<int64_t>(r) * a.dst_pitch;
+    if constexpr (kFull) {
+        Pix<T, C>::store(orow, c, extra);
+    } else {
+        float *out = reinterpret_cast<float *>(orow) + c * C;
 #pragma unroll
-    for (int ch = 0; ch < C; ++ch)
-        out[ch] += extra[ch];
+        for (int ch = 0; ch < C; ++ch)
+            out[ch] += extra[ch];
+    }
 }
 
-template <int FILTER, int C>
+template <int FILTER, typename T, int C>
 hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
 {
     constexpr int P = (C == 1) ? 4 : 1;
     constexpr int32_t kStrip = 16;
     const int32_t cols_per_block = 256 * P;
-    hipLaunchKernelGGL((k_bwd_up2<FILTER, C, P>),
+    hipLaunchKernelGGL((k_bwd_up2<FILTER, T, C, P>),
                        dim3((a.in_w + cols_per_block - 1) / cols_per_block, (a.in_h + kStrip - 1) / kStrip,
                             a.planes),
                        dim3(256), 0, stream, a, kStrip);
     const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
     const int32_t border = ((a.in_h > 1) ? 2 * a.in_w : a.in_w) + ((a.in_w > 1) ? 2 * inner : inner);
-    hipLaunchKernelGGL((k_bwd_up2_border<FILTER, C>), dim3((border + 255) / 256, a.planes), dim3(256), 0,
+    hipLaunchKernelGGL((k_bwd_up2_border<FILTER, T, C>), dim3((border + 255) / 256, a.planes), dim3(256), 0,
                        stream, a);
     return hipGetLastError();
 }
@@ -493,9 +506,8 @@ BwdPlan plan_backward(const ResizeArgs &a)
 template <int FILTER, typename T, int C>
 hipError_t launch_bwd_typed(const ResizeArgs &a, hipStream_t stream)
 {
-    if constexpr (std::is_same_v<T, float>)
-        if (a.out_w == 2 * a.in_w && a.out_h == 2 * a.in_h)
-            return launch_bwd_up2<FILTER, C>(a, stream);
+    if (a.out_w == 2 * a.in_w && a.out_h == 2 * a.in_h)
+        return launch_bwd_up2<FILTER, T, C>(a, stream);
     const BwdPlan p = plan_backward<FILTER, C>(a);
     if (p.lds == 0)
         return hipErrorInvalidConfiguration;
