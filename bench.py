@@ -46,6 +46,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 78.6  # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 ROTATE_BYTES = 1 << 30
 KERNEL_SOURCES = ["xr_forward.hip", "xr_device.hpp", "xr_internal.h"]
 
@@ -184,7 +185,15 @@ def headline(args, torch, xr, fields):
                 "alg_bytes_per_launch": alg, "kernel_ms": {k: round(v, 5) for k, v in stats.items()},
                 "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2),
                 # the FP32 VALU check: instruction issue time from the counters
-                "valu": read_valu("sq_k_strip_up2_bicubic_x2_u8rgba.txt", resolved, kernel_s)}
+                "valu": read_valu("sq_k_strip_up2_bicubic_x2_u8rgba.txt", resolved, kernel_s),
+                # and the algorithmic arithmetic rate: separable Keys x2 takes 24
+                # FP32 multiply-adds per output pixel (4 taps x 4 channels
+                # vertically, half that horizontally per output row), against
+                # the non-packed FP32 peak (256 CUs x 64 lanes x 2 flops x 2.4 GHz)
+                "fp32": {"fma_per_px": 24,
+                         "achieved_tflops": round(2 * 24 * out_px / kernel_s / 1e12, 2),
+                         "peak_tflops": FP32_PEAK_TFLOPS,
+                         "frac": round(2 * 24 * out_px / kernel_s / 1e12 / FP32_PEAK_TFLOPS, 4)}}
     return {
         "value": value, "wall": wall, "roofline": roofline, "tile": repr(resolved), "tune": tune,
         "n_buf": n_buf, "src_host": srcs[0].cpu().numpy(),
