@@ -1,6 +1,6 @@
 """Shared helpers of the GPU parity tests: comparison rules against the oracle.
 
-Tolerances (derived in the design doc from the float32 evaluation order):
+Tolerances (derived from the float32 evaluation order):
 * uint8, dyadic scale ratios (every weight k / 2^m): the float32 sums are exact,
   so the GPU must equal rint-half-even + clamp of the float64 oracle on every
   pixel, rounding ties included;
