@@ -130,6 +130,10 @@ def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
         ends[i].record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # GPU time from the first launch's start to the last one's end: for
+    # launches of a few microseconds this is the back-to-back rate, which
+    # per-launch event pairs (dominated by dispatch latency) overstate
+    time_launches.span_ms = starts[0].elapsed_time(ends[-1])
     return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
@@ -463,7 +467,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
                 "cpu_sample": f"{n_rows} rows x {passes} passes" if passes > 1 else f"{n_rows} rows"}
 
     def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel",
-                rotate=True):
+                rotate=True, all_kinds=False):
         src0 = make_src()
         in_bytes = src0.numel() * src0.element_size()
         out_bytes = math.prod(out_shape) * src0.element_size()
@@ -476,9 +480,9 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         chans = src0.shape[-1] if layout == "hwc" and src0.dim() == 3 else 1
         in_hw = src0.shape[:2] if layout == "hwc" else src0.shape[-2:]
         out_hw = out_shape[:2] if layout == "hwc" else out_shape[-2:]
-        # the antialiased filters: the library's own list (gather and LDS
-        # blocks, those whose LDS fits); the others: strip shapes
-        cands = None if mode.endswith("_aa") else [
+        # the antialiased filters and tiny images: the library's own list
+        # (with the gather shapes); the others: strip shapes
+        cands = None if (mode.endswith("_aa") or all_kinds) else [
             c for c in xr.tune_candidates(mode, xr._DTYPES[src0.dtype], chans, in_hw[1], in_hw[0],
                                           out_hw[1], out_hw[0])
             if c.kernel in (xr.XR_KERNEL_STRIP, xr.XR_KERNEL_STRIP_LDS)]
@@ -492,7 +496,7 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         # pixels: H * W for interleaved images, N * C * H * W for planar tensors
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
         out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
-                     "buffers": n_buf,
+                     "buffers": n_buf, "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2),
                      "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
                      "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4),
                      **oracle_rate(src0, out_hw, mode, layout, mapping)}
@@ -513,10 +517,10 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
     measure("bicubic_paper_map_x3_u8_rgba", lambda: u8, (12288, 12288, 4), "bicubic", mapping="paper")
     del fld, unit, u8
     measure("c1_bilinear_x2_u8_512", lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev),
-            (1024, 1024), "bilinear")
+            (1024, 1024), "bilinear", all_kinds=True)
     measure("c1_bilinear_x2_u8_512_unrotated",
             lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev), (1024, 1024), "bilinear",
-            rotate=False)
+            rotate=False, all_kinds=True)
     measure("c4_bilinear_x2_f32_nchw_fwd", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
             (32, 3, 2048, 2048), "bilinear", layout="nchw")
     # C4 adjoint (exact x2 float32: register walk), and the owner-computes

@@ -854,8 +854,9 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     const int ppx_c1[3] = {4, 8, 16};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
     const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}, {256, 2}, {512, 1}};
-    // strip heights 8m-2 make the x2 walk's source-row groups come out even
-    const int ppy_list[] = {6, 14, 22, 30, 46, 62};
+    // strip heights 8m-2 make the x2 walk's source-row groups come out even;
+    // 1 and 2 rows give small images enough workgroups
+    const int ppy_list[] = {1, 2, 6, 14, 22, 30, 46, 62};
     for (int k = 0; k < 3; ++k) {
         const int ppx = ppx_list[k];
         if (!xr::strip_ppx_supported(dtype, channels, ppx))

@@ -32,6 +32,8 @@ TILES = {
     "strip_any": xr.tile(xr.XR_KERNEL_STRIP_ANY, 128, 2, 0, 5),
     "strip_xcd": xr.tile(xr.XR_KERNEL_STRIP, 512, 1, 0, 9, 1),
     "strip_any_xcd": xr.tile(xr.XR_KERNEL_STRIP_ANY, 64, 2, 0, 3, 1),
+    "strip_row1": xr.tile(xr.XR_KERNEL_STRIP, 64, 1, 0, 1),     # one output row per thread
+    "strip_row2_xcd": xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 0, 2, 1),
     "strip_lds": xr.tile(xr.XR_KERNEL_STRIP_LDS, 64, 1, 0, 7),
     "strip_lds_xcd": xr.tile(xr.XR_KERNEL_STRIP_LDS, 256, 1, 0, 3, 1),
 }
