@@ -137,6 +137,30 @@ def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
     return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
+def graph_launch_us(launch, n_buffers: int, torch, reps: int = 100) -> float:
+    """Microseconds per launch of `reps` launches captured in one HIP graph
+    and replayed: no host submission between kernels, so for launches of a
+    few microseconds this is the kernel rate that per-launch events (which
+    then include the host's submission gap) overstate."""
+    graph = torch.cuda.CUDAGraph()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            for i in range(reps):
+                launch(i % n_buffers)
+    torch.cuda.current_stream().wait_stream(stream)
+    graph.replay()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    del graph
+    return e0.elapsed_time(e1) / reps * 1e3
+
+
 def group_stats(ms, group: int = 100):
     groups = [ms[i:i + group] for i in range(0, len(ms), group) if len(ms[i:i + group]) == group]
     if not groups:
@@ -493,10 +517,12 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
 
         wall, ms = time_launches(launch, n_buf, steps, warmup, torch)
         k_s = sum(ms) / len(ms) / 1e3
+        g_us = graph_launch_us(launch, n_buf, torch)
         # pixels: H * W for interleaved images, N * C * H * W for planar tensors
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
         out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
                      "buffers": n_buf, "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2),
+                     "graph_us": round(g_us, 2),
                      "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
                      "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4),
                      **oracle_rate(src0, out_hw, mode, layout, mapping)}

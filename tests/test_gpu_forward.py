@@ -256,6 +256,24 @@ def test_antialiased_tiled_matches_gather_on_many_blocks(case):
     compare(got[rows], img, out_h, out_w, MODES[mode], rows=rows, what=f"{case}")
 
 
+@pytest.mark.parametrize("dtype", [np.float16, np.float32], ids=["f16", "f32"])
+@pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
+def test_antialiased_planar(dtype, mode):
+    """NCHW tensors (planes = N x C): every plane against the oracle, and the
+    LDS-tiled kernel bitwise equal to the gather."""
+    n, c, in_h, in_w, out_h, out_w = 2, 3, 91, 130, 30, 41
+    x_np = np.ascontiguousarray(
+        fields.field_unit(in_h, in_w, n * c, seed=77, dtype=dtype).transpose(2, 0, 1)).reshape(n, c, in_h, in_w)
+    x = torch.from_numpy(x_np).to(DEV)
+    y = xr.resize(x, (out_h, out_w), mode, layout="nchw")
+    g = xr.resize(x, (out_h, out_w), mode, layout="nchw", tile=xr.tile(xr.XR_KERNEL_GATHER, 32, 4))
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint8), g.cpu().numpy().view(np.uint8))
+    planes = x_np.reshape(n * c, in_h, in_w, 1)
+    compare(got.reshape(n * c, out_h, out_w, 1), planes, out_h, out_w, MODES[mode], what=f"planar {mode}")
+
+
 @pytest.mark.parametrize("mode", ["bilinear_aa", "bicubic_aa"])
 def test_antialiased_bands_and_limits(mode):
     img = fields.field_unit(120, 64, 4, seed=3, dtype=np.float32)
