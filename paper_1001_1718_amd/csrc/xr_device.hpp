@@ -48,6 +48,37 @@ __device__ __forceinline__ void axis_tap(int32_t x, int32_t n_in, int32_t n_out,
     omt = __fdiv_rn(static_cast<float>(den - rem), static_cast<float>(den));
 }
 
+// a / b correctly rounded from y = RN(1 / b): q0 = RN(a y), then one
+// correction with the exact residual a - q0 b (an FMA). For integers
+// 0 <= a <= b <= 65536 the result equals the IEEE quotient (checked
+// exhaustively on the host for every such pair), so callers that divide many
+// numerators by one denominator share one division.
+__device__ __forceinline__ float div_rcp(float a, float b, float y)
+{
+    const float q0 = a * y;
+    const float r = __builtin_fmaf(-q0, b, a);
+    return __builtin_fmaf(r, y, q0);
+}
+
+// axis_tap with the reciprocal of its denominator 2 n_out supplied
+// (rcp = RN(1 / (2 n_out))): the same x0, t and 1 - t bit for bit.
+__device__ __forceinline__ void axis_tap_rcp(int32_t x, int32_t n_in, int32_t n_out, int32_t o, float rcp,
+                                             int32_t &x0, float &t, float &omt)
+{
+    const int32_t num = (2 * x + o) * n_in - o * n_out;
+    const int32_t den = 2 * n_out;
+    int32_t q = num / den;
+    int32_t rem = num - q * den;
+    if (rem < 0) {
+        q -= 1;
+        rem += den;
+    }
+    x0 = q;
+    const float d = static_cast<float>(den);
+    t = div_rcp(static_cast<float>(rem), d, rcp);
+    omt = div_rcp(static_cast<float>(den - rem), d, rcp);
+}
+
 // The tap of FILTER for output x: eqs. 1-4 for bilinear and bicubic; for
 // nearest neighbour the source pixel whose area contains the mapped point,
 // floor(s + o/2) = floor((2x+o) n_in / (2 n_out)) (pixel i covers
@@ -63,6 +94,19 @@ __device__ __forceinline__ void source_tap(int32_t x, int32_t n_in, int32_t n_ou
         omt = 1.0f;
     } else {
         axis_tap(x, n_in, n_out, o, x0, t, omt);
+    }
+}
+
+// source_tap with rcp = RN(1 / (2 n_out)) supplied (per-row callers).
+template <int FILTER>
+__device__ __forceinline__ void source_tap_rcp(int32_t x, int32_t n_in, int32_t n_out, int32_t o, float rcp,
+                                               int32_t &x0, float &t, float &omt)
+{
+    if constexpr (FILTER == kNearest) {
+        (void)rcp;
+        source_tap<FILTER>(x, n_in, n_out, o, x0, t, omt);
+    } else {
+        axis_tap_rcp(x, n_in, n_out, o, rcp, x0, t, omt);
     }
 }
 

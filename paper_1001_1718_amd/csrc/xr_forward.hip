@@ -515,8 +515,10 @@ struct StripBody {
         const int32_t y_end = a.dst_row0 + r_end;
         int32_t y0, y0_last;
         float ty, uy, tl, ul;
-        source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
-        source_tap<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, y0_last, tl, ul);
+        // one division per strip: the rows' taps use its reciprocal
+        const float rcp_h = __fdiv_rn(1.0f, static_cast<float>(2 * a.out_h));
+        source_tap_rcp<FILTER>(y, a.in_h, a.out_h, a.map_off, rcp_h, y0, ty, uy);
+        source_tap_rcp<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, rcp_h, y0_last, tl, ul);
         float wy[K];
         weights<FILTER>(ty, uy, wy);
         int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
@@ -548,7 +550,7 @@ struct StripBody {
                 }
                 ++y;
                 if (y < y_end) {
-                    source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
+                    source_tap_rcp<FILTER>(y, a.in_h, a.out_h, a.map_off, rcp_h, y0, ty, uy);
                     weights<FILTER>(ty, uy, wy);
                     last = y0 + TP::LO + K - 1;
                 }
@@ -719,8 +721,10 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
     const int32_t y_end = a.dst_row0 + r_end;
     int32_t y0, y0_last;
     float ty, uy, tl, ul;
-    source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
-    source_tap<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, y0_last, tl, ul);
+    // one division per strip: the rows' taps use its reciprocal
+    const float rcp_h = __fdiv_rn(1.0f, static_cast<float>(2 * a.out_h));
+    source_tap_rcp<FILTER>(y, a.in_h, a.out_h, a.map_off, rcp_h, y0, ty, uy);
+    source_tap_rcp<FILTER>(y_end - 1, a.in_h, a.out_h, a.map_off, rcp_h, y0_last, tl, ul);
     float wy[K];
     weights<FILTER>(ty, uy, wy);
     int32_t last = y0 + TP::LO + K - 1;  // last tap row of output y
@@ -785,7 +789,7 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
             }
             ++y;
             if (y < y_end) {
-                source_tap<FILTER>(y, a.in_h, a.out_h, a.map_off, y0, ty, uy);
+                source_tap_rcp<FILTER>(y, a.in_h, a.out_h, a.map_off, rcp_h, y0, ty, uy);
                 weights<FILTER>(ty, uy, wy);
                 last = y0 + TP::LO + K - 1;
             }
