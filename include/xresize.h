@@ -204,7 +204,8 @@ int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t 
  * xr_batch_workspace_bytes(n): bytes of device workspace for n jobs.
  * xr_batch_prepare: validates every job exactly like xr_resize_*, splits
  *   every output into tiles of `tile` (NULL = the shape xr_batch_autotune
- *   chose for this dtype, else 256x1 threads with 14-row strips), orders the jobs
+ *   chose for this dtype, else 256x1 threads with 14-row strips; two output
+ *   columns per thread whatever tile.ppt_x says), orders the jobs
  *   largest-first, and uploads the job table and tile prefix sums to
  *   `dev_ws` (device memory, 256-byte aligned, >= xr_batch_workspace_bytes(n))
  *   with an asynchronous copy on `stream`. The host copy of `jobs` may be
@@ -231,7 +232,7 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
  * Autotuner of the batched launch (the paper's tile-shape question, sections
  * III.A and IV, asked for a whole batch): prepares `dev_ws` with each
  * candidate shape in turn (NULL = built-in list: 64x4, 128x2 and 256x1
- * threads, strips of 4 to 46 rows; ppt_x is always 4), times `groups` groups
+ * threads, strips of 4 to 94 rows; ppt_x is always 2), times `groups` groups
  * of `reps` launches with HIP events on `stream`, and keeps the shape with
  * the smallest median time per launch. On return `dev_ws` is prepared with
  * that shape, *best / *best_ms (either may be NULL) hold it, and later

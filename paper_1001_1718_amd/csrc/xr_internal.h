@@ -127,7 +127,10 @@ constexpr size_t kLdsBudget = 64 * 1024;
 // ResizeArgs; pixels of fewer than 4 bytes are staged as 4-byte words).
 bool strip_lds_fits(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w,
                     int32_t block_w, bool aligned4);
-// Output columns per thread of the batched kernel (both channel counts).
-constexpr int32_t kBatchPpx = 4;
+// Output columns per thread of the batched kernel (both channel counts). The
+// kernel holds every job kind's walk, so its registers are the largest
+// walk's: two columns keep it at 4 waves per SIMD (four columns needed 166
+// VGPRs, 3 waves, and ran 14% slower on the uneven batch).
+constexpr int32_t kBatchPpx = 2;
 
 }  // namespace xr

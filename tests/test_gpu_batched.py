@@ -157,8 +157,9 @@ def test_batch_autotune_picks_a_candidate_and_keeps_results():
     jobs, pairs = _make_batch(seed=3, count=24, side_hi=512, content="field")
     ref = _per_image(pairs)
     b = xr.Batch(pairs)
-    cands = [xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 4, 8), xr.tile(xr.XR_KERNEL_STRIP, 256, 1, 4, 14),
-             xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 4, 30)]
+    # the batched kernel takes two output columns per thread (ppt_x 2)
+    cands = [xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 2, 8), xr.tile(xr.XR_KERNEL_STRIP, 256, 1, 2, 14),
+             xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 2, 30)]
     best, ms = b.autotune(candidates=cands, reps=2, groups=3)
     assert ms > 0 and best.as_tuple() in [c.as_tuple() for c in cands]
     for _, d, _ in pairs:
@@ -168,7 +169,7 @@ def test_batch_autotune_picks_a_candidate_and_keeps_results():
     assert all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
     # the built-in candidate list, then a batch prepared with the tuned default
     best, ms = b.autotune(reps=1, groups=1)
-    assert ms > 0 and best.kernel == xr.XR_KERNEL_STRIP and best.ppt_x == 4
+    assert ms > 0 and best.kernel == xr.XR_KERNEL_STRIP and best.ppt_x == 2
     b2 = xr.Batch(pairs)
     for _, d, _ in pairs:
         d.zero_()
