@@ -480,8 +480,12 @@ BwdPlan plan_backward(const ResizeArgs &a)
     // (1 - LO + 1/2) out / in + 1 at a clamped border; rows alike
     p.nmax = static_cast<int32_t>((static_cast<int64_t>(K) * a.out_w + a.in_w - 1) / a.in_w + 2);
     p.nmax_y = static_cast<int32_t>((static_cast<int64_t>(K) * a.out_h + a.in_h - 1) / a.in_h + 2);
+    // first tile height: tall for shrinking and identity (few output rows per
+    // source row), short for upscales (measured: x0.75 bilinear 0.26 -> 0.19 ms
+    // at 32 rows, x1.5 bicubic 0.75 -> 0.71 ms at 8)
+    const int32_t th0 = a.out_h <= a.in_h ? 32 : 8;
     p.tw = kBwdThreads / C;
-    p.th = 16;
+    p.th = th0;
     for (;;) {
         // output rows touching th source rows: at most (th + K - 1) * out/in + 2
         const int64_t rows = (static_cast<int64_t>(p.th + K - 1) * a.out_h + a.in_h - 1) / a.in_h + 2;
@@ -495,7 +499,7 @@ BwdPlan plan_backward(const ResizeArgs &a)
             p.th /= 2;
         } else if (p.tw > 16) {
             p.tw /= 2;
-            p.th = 16;
+            p.th = th0;
         } else {
             p.lds = 0;
             return p;
