@@ -178,7 +178,7 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
  *            filters it separably (rows, then columns). Both give identical
  *            bits. Strip kinds (and XR_KERNEL_AUTO before tuning) take the
  *            first LDS block of 64x4, 64x2, 32x2, 16x2 that fits, else a 64x4
- *            gather. XR_ERR_ARG when the workgroup's LDS exceeds 64 KiB: the
+ *            gather. XR_ERR_ARG when the workgroup's LDS exceeds 96 KiB: the
  *            weight tables, 4 (2 bw + 2 bh + bw kx + bh ky) bytes with
  *            k = floor(2 R sigma) + 1, plus for LDS blocks the source window
  *            (W x H pixels, W = floor(((bw - 1) N_in + 2 R max(N_in, N_out)) / N_out) + 2
