@@ -9,9 +9,8 @@
 // pixel is written exactly once with a plain store: no global atomics, no
 // clearing pass, and pixels no output touches come out as zero.
 //
-//  phase 0  taps (first row, K weights) of the output rows of the region,
-//           and for each tile column c the outputs x whose taps reach it with
-//           their summed weight w(x, c);
+//  phase 0  for each tile column c the outputs x whose taps reach it with
+//           their summed weight w(x, c), and the same for each tile row;
 //  phase 1  horizontal adjoint, gather: u[y][c] = sum over x ascending of
 //           w(x, c) * g[y][x];
 //  phase 2  vertical adjoint, gather: grad[r][c] = sum over the output rows y
@@ -19,7 +18,7 @@
 //
 // Every sum has a fixed order, so the result is deterministic (bit for bit
 // the same on every run and for every tiling of the launch). The exact-x2
-// float32 path below is deterministic as well.
+// path below (float32 and float16) is deterministic as well.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
