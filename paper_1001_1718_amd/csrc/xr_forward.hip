@@ -19,9 +19,15 @@
 //               everywhere, a contiguous run of 2 ppt_x - 2 + K source
 //               pixels per row, two source rows per output row.
 //  k_strip_lds  any scale, each source row staged once per workgroup in LDS.
+//  k_batched    one persistent launch over the tiles of many jobs, each tile
+//               running the k_strip walk of its job.
+//  k_gather_aa, k_tile_aa  the antialiased filters (support stretched when
+//               shrinking): one pixel per thread from memory, or the block's
+//               source window staged in LDS and filtered separably.
 //
-// All three evaluate each output with the same float32 operation sequence
-// (xr_device.hpp), so their results are bit-identical.
+// The bilinear and bicubic kernels evaluate each output with the same float32
+// operation sequence (xr_device.hpp), so their results are bit-identical; so
+// are the two antialiased kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
