@@ -232,7 +232,7 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
  * Autotuner of the batched launch (the paper's tile-shape question, sections
  * III.A and IV, asked for a whole batch): prepares `dev_ws` with each
  * candidate shape in turn (NULL = built-in list: 64x4, 128x2 and 256x1
- * threads, strips of 4 to 94 rows; ppt_x is always 2), times `groups` groups
+ * threads, strips of 4 to 190 rows; ppt_x is always 2), times `groups` groups
  * of `reps` launches with HIP events on `stream`, and keeps the shape with
  * the smallest median time per launch. On return `dev_ws` is prepared with
  * that shape, *best / *best_ms (either may be NULL) hold it, and later

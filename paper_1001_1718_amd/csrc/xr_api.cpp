@@ -711,7 +711,7 @@ int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candida
         cand.assign(candidates, candidates + n_candidates);
     } else {
         const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}};
-        const int ppy_list[] = {4, 8, 14, 22, 30, 46, 62, 94};
+        const int ppy_list[] = {4, 8, 14, 22, 30, 46, 62, 94, 126, 190};
         for (const auto &b : blocks)
             for (int ppy : ppy_list)
                 cand.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], xr::kBatchPpx, ppy, 0});
