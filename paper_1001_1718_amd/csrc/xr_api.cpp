@@ -304,7 +304,7 @@ xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w
         t.block_w = 256;
         t.block_h = 1;
         t.ppt_x = c4 ? 4 : 8;
-        first = 14;
+        first = 22;  // the tuner's usual choice for large x2 images
     } else if (2 * out_w == in_w && 2 * out_h == in_h) {
         t.block_w = 512;
         t.block_h = 1;
@@ -321,7 +321,7 @@ xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w
         return wcols * ((static_cast<int64_t>(rows) + u.ppt_y - 1) / u.ppt_y) * planes;
     };
     const int64_t target = 8192;
-    const int steps[] = {first, 6, 2, 1};
+    const int steps[] = {first, 14, 6, 2, 1};
     for (int ppy : steps) {
         if (ppy > first)
             continue;
