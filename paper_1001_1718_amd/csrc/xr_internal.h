@@ -1,5 +1,5 @@
 // Internal interface between the C-ABI layer (xr_api.cpp) and the kernels
-// (xr_kernels.hip). Not installed; callers use include/xresize.h.
+// (xr_forward.hip, xr_backward.hip). Not installed; callers use include/xresize.h.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
