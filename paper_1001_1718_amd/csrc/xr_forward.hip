@@ -332,6 +332,8 @@ __device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned ch
 // sequence is exactly k_gather_aa's (taps ascending per row, rows ascending),
 // so the two kernels agree bit for bit. The window is at most win_w x win_h
 // pixels (bounded on the host from the scale).
+constexpr int kAaRegTaps = 12;  // register-held horizontal weights (bicubic to 1/2.75)
+
 template <int R, typename T, int C>
 __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int32_t ky, int32_t win_w,
                                                   int32_t win_h)
@@ -397,27 +399,49 @@ __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int3
                 store_raw<PB, PB>(win + off[k], v[k]);
     }
     __syncthreads();
-    // horizontal pass: window row r, tile column c (threads of one column
-    // take rows ty, ty + bh, ...)
+    // horizontal pass: window row r, tile column hc (threads of one column
+    // take rows ty, ty + bh, ...). A column's weights are the same on every
+    // row, so up to kAaRegTaps of them are held in registers.
     const int32_t hc = threadIdx.x;
     const int32_t hx0 = xlo[hc] - wx0, hnx = xn[hc];
     const float *hwx = xw + hc * kx;
-    for (int32_t r = threadIdx.y; r < wh; r += bh) {
-        const int32_t c = hc;
-        const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
-        const int32_t x0 = hx0, nx = hnx;
-        const float *wxr = hwx;
-        float h[C], p[C];
-        Pix<T, C>::load(wrow, x0, p);
-        fma_first(h, wxr[0], p);
-        for (int32_t k = 1; k < nx; ++k) {
-            Pix<T, C>::load(wrow, x0 + k, p);
-            fma_next(h, wxr[k], p);
-        }
-        float *hp = hbuf + (static_cast<int64_t>(r) * bw + c) * C;
+    if (kx <= kAaRegTaps) {
+        float wr[kAaRegTaps];
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            hp[ch] = h[ch];
+        for (int k = 0; k < kAaRegTaps; ++k)
+            wr[k] = k < hnx ? hwx[k] : 0.0f;
+        for (int32_t r = threadIdx.y; r < wh; r += bh) {
+            const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
+            float h[C], p[C];
+            Pix<T, C>::load(wrow, hx0, p);
+            fma_first(h, wr[0], p);
+#pragma unroll
+            for (int k = 1; k < kAaRegTaps; ++k) {
+                if (k < hnx) {
+                    Pix<T, C>::load(wrow, hx0 + k, p);
+                    fma_next(h, wr[k], p);
+                }
+            }
+            float *hp = hbuf + (static_cast<int64_t>(r) * bw + hc) * C;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                hp[ch] = h[ch];
+        }
+    } else {
+        for (int32_t r = threadIdx.y; r < wh; r += bh) {
+            const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
+            float h[C], p[C];
+            Pix<T, C>::load(wrow, hx0, p);
+            fma_first(h, hwx[0], p);
+            for (int32_t k = 1; k < hnx; ++k) {
+                Pix<T, C>::load(wrow, hx0 + k, p);
+                fma_next(h, hwx[k], p);
+            }
+            float *hp = hbuf + (static_cast<int64_t>(r) * bw + hc) * C;
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                hp[ch] = h[ch];
+        }
     }
     __syncthreads();
     const int32_t px = blockIdx.x * bw + threadIdx.x;
