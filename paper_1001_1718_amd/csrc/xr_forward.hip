@@ -323,20 +323,24 @@ __device__ __forceinline__ void copy_pixel(unsigned char *dst, const unsigned ch
     }
 }
 
-// The antialiased filter on a block_w x block_h tile of output pixels with
-// the source window staged in LDS (separable): the same weight tables as
-// k_gather_aa; then the tile's source window (rows ylo(first) .. yhi(last),
-// columns xlo(first) .. xhi(last)) is copied to LDS with coalesced loads; the
-// horizontal pass filters every window row for every tile column into an LDS
-// row buffer; each thread then sums its rows. Per pixel the float32
-// sequence is exactly k_gather_aa's (taps ascending per row, rows ascending),
-// so the two kernels agree bit for bit. The window is at most win_w x win_h
-// pixels (bounded on the host from the scale).
+// The antialiased filter on block_w x block_h tiles of output pixels with
+// the source window staged in LDS (separable). A workgroup takes `tpb`
+// vertically adjacent tiles of one tile column: the column tables (taps and
+// kx weights per output column, the same as k_gather_aa's) are built once,
+// the row tables once per tile. Per tile the source window (rows ylo(first)
+// .. yhi(last), columns xlo(first) .. xhi(last)) is copied to LDS with
+// coalesced loads, the horizontal pass filters every window row for every
+// tile column into an LDS row buffer, and each thread then sums its rows. Per
+// pixel the float32 sequence is exactly k_gather_aa's (taps ascending per
+// row, rows ascending), so the two kernels agree bit for bit. The window is
+// at most win_w x win_h pixels (bounded on the host from the scale).
 constexpr int kAaRegTaps = 12;  // register-held horizontal weights (bicubic to 1/2.75)
+constexpr int32_t kAaTilesPerBlock = 4;  // most tiles a workgroup walks down its column
+constexpr int64_t kAaMinBlocks = 1024;    // workgroups the multi-tile grid keeps
 
 template <int R, typename T, int C>
 __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int32_t ky, int32_t win_w,
-                                                  int32_t win_h)
+                                                  int32_t win_h, int32_t tpb)
 {
     constexpr int PB = Pix<T, C>::kBytes;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -353,117 +357,127 @@ __global__ void __launch_bounds__(1024) k_tile_aa(ResizeArgs a, int32_t kx, int3
     unsigned char *win = lds + (table_bytes + 15) / 16 * 16;
     float *hbuf = reinterpret_cast<float *>(win + (static_cast<int64_t>(win_w) * win_h * PB + 15) / 16 * 16);
     const int32_t tid = threadIdx.y * bw + threadIdx.x;
-    for (int32_t t = tid; t < bw + bh; t += nthreads) {
-        if (t < bw) {
-            const int32_t x = min(static_cast<int32_t>(blockIdx.x) * bw + t, a.out_w - 1);
-            aa_table<R>(x, a.in_w, a.out_w, kx, xlo + t, xn + t, xw + t * kx);
-        } else {
-            const int32_t u = t - bw;
-            const int32_t y = a.dst_row0 + min(static_cast<int32_t>(blockIdx.y) * bh + u, a.dst_rows - 1);
-            aa_table<R>(y, a.in_h, a.out_h, ky, ylo + u, yn + u, yw + u * ky);
-        }
-    }
-    __syncthreads();
-    // the tile's source window (tap ranges are monotone in x and y)
-    const int32_t wx0 = xlo[0];
-    const int32_t ww = min(xlo[bw - 1] + xn[bw - 1] - wx0, win_w);
-    const int32_t wy0 = ylo[0];
-    const int32_t wh = min(ylo[bh - 1] + yn[bh - 1] - wy0, win_h);
     const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
-    // NB loads in flight per thread before any LDS store. Element i of the
-    // window is (i / ww, i % ww); a thread's elements step by nthreads, i.e.
-    // by dr rows and dc columns with a carry, so no division per element.
-    constexpr int NB = 8;
-    const int32_t total = ww * wh;
-    const int32_t dr = nthreads / ww, dc = nthreads - dr * ww;
-    int32_t r = tid / ww, c = tid - (tid / ww) * ww;
-    const unsigned char *wsrc = src + static_cast<int64_t>(wy0 - a.src_row0) * a.src_pitch +
-                                static_cast<int64_t>(wx0) * PB;
-    for (int32_t base = tid; base < total; base += nthreads * NB) {
-        RawBuf<PB, PB> v[NB];
-        int32_t off[NB];
-#pragma unroll
-        for (int k = 0; k < NB; ++k) {
-            // past the end: reload the window's last element (a valid address)
-            const bool in = base + k * nthreads < total;
-            const int32_t rr = in ? r : wh - 1, cc = in ? c : ww - 1;
-            off[k] = (rr * win_w + cc) * PB;
-            v[k] = load_raw<PB, PB>(wsrc + static_cast<int64_t>(rr) * a.src_pitch + cc * PB);
-            c += dc;
-            r += dr + (c >= ww ? 1 : 0);
-            c -= c >= ww ? ww : 0;
+    const int32_t n_tiles_y = (a.dst_rows + bh - 1) / bh;
+    const int32_t tile_end = min(static_cast<int32_t>(blockIdx.y + 1) * tpb, n_tiles_y);
+    // Every bound below is uniform over the workgroup, and no thread leaves
+    // the loop early, so every thread reaches every barrier.
+    for (int32_t by = static_cast<int32_t>(blockIdx.y) * tpb; by < tile_end; ++by) {
+        const bool first = by == static_cast<int32_t>(blockIdx.y) * tpb;
+        for (int32_t t = tid + (first ? 0 : bw); t < bw + bh; t += nthreads) {
+            if (t < bw) {
+                const int32_t x = min(static_cast<int32_t>(blockIdx.x) * bw + t, a.out_w - 1);
+                aa_table<R>(x, a.in_w, a.out_w, kx, xlo + t, xn + t, xw + t * kx);
+            } else {
+                const int32_t u = t - bw;
+                const int32_t y = a.dst_row0 + min(by * bh + u, a.dst_rows - 1);
+                aa_table<R>(y, a.in_h, a.out_h, ky, ylo + u, yn + u, yw + u * ky);
+            }
         }
+        __syncthreads();
+        // the tile's source window (tap ranges are monotone in x and y)
+        const int32_t wx0 = xlo[0];
+        const int32_t ww = min(xlo[bw - 1] + xn[bw - 1] - wx0, win_w);
+        const int32_t wy0 = ylo[0];
+        const int32_t wh = min(ylo[bh - 1] + yn[bh - 1] - wy0, win_h);
+        // NB loads in flight per thread before any LDS store. Element i of the
+        // window is (i / ww, i % ww); a thread's elements step by nthreads,
+        // i.e. by dr rows and dc columns with a carry, so no division per
+        // element.
+        constexpr int NB = 8;
+        const int32_t total = ww * wh;
+        const int32_t dr = nthreads / ww, dc = nthreads - dr * ww;
+        int32_t r = tid / ww, c = tid - (tid / ww) * ww;
+        const unsigned char *wsrc = src + static_cast<int64_t>(wy0 - a.src_row0) * a.src_pitch +
+                                    static_cast<int64_t>(wx0) * PB;
+        for (int32_t base = tid; base < total; base += nthreads * NB) {
+            RawBuf<PB, PB> v[NB];
+            int32_t off[NB];
 #pragma unroll
-        for (int k = 0; k < NB; ++k)
-            if (base + k * nthreads < total)
-                store_raw<PB, PB>(win + off[k], v[k]);
-    }
-    __syncthreads();
-    // horizontal pass: window row r, tile column hc (threads of one column
-    // take rows ty, ty + bh, ...). A column's weights are the same on every
-    // row, so up to kAaRegTaps of them are held in registers.
-    const int32_t hc = threadIdx.x;
-    const int32_t hx0 = xlo[hc] - wx0, hnx = xn[hc];
-    const float *hwx = xw + hc * kx;
-    if (kx <= kAaRegTaps) {
-        float wr[kAaRegTaps];
+            for (int k = 0; k < NB; ++k) {
+                // past the end: reload the window's last element (a valid address)
+                const bool in = base + k * nthreads < total;
+                const int32_t rr = in ? r : wh - 1, cc = in ? c : ww - 1;
+                off[k] = (rr * win_w + cc) * PB;
+                v[k] = load_raw<PB, PB>(wsrc + static_cast<int64_t>(rr) * a.src_pitch + cc * PB);
+                c += dc;
+                r += dr + (c >= ww ? 1 : 0);
+                c -= c >= ww ? ww : 0;
+            }
 #pragma unroll
-        for (int k = 0; k < kAaRegTaps; ++k)
-            wr[k] = k < hnx ? hwx[k] : 0.0f;
-        for (int32_t r = threadIdx.y; r < wh; r += bh) {
-            const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
-            float h[C], p[C];
-            Pix<T, C>::load(wrow, hx0, p);
-            fma_first(h, wr[0], p);
+            for (int k = 0; k < NB; ++k)
+                if (base + k * nthreads < total)
+                    store_raw<PB, PB>(win + off[k], v[k]);
+        }
+        __syncthreads();
+        // horizontal pass: window row r, tile column hc (threads of one
+        // column take rows ty, ty + bh, ...). A column's weights are the same
+        // on every row, so up to kAaRegTaps of them are held in registers.
+        const int32_t hc = threadIdx.x;
+        const int32_t hx0 = xlo[hc] - wx0, hnx = xn[hc];
+        const float *hwx = xw + hc * kx;
+        if (kx <= kAaRegTaps) {
+            float wr[kAaRegTaps];
 #pragma unroll
-            for (int k = 1; k < kAaRegTaps; ++k) {
-                if (k < hnx) {
-                    Pix<T, C>::load(wrow, hx0 + k, p);
-                    fma_next(h, wr[k], p);
+            for (int k = 0; k < kAaRegTaps; ++k)
+                wr[k] = k < hnx ? hwx[k] : 0.0f;
+            for (int32_t rr = threadIdx.y; rr < wh; rr += bh) {
+                const unsigned char *wrow = win + static_cast<int64_t>(rr) * win_w * PB;
+                float h[C], p[C];
+                Pix<T, C>::load(wrow, hx0, p);
+                fma_first(h, wr[0], p);
+#pragma unroll
+                for (int k = 1; k < kAaRegTaps; ++k) {
+                    if (k < hnx) {
+                        Pix<T, C>::load(wrow, hx0 + k, p);
+                        fma_next(h, wr[k], p);
+                    }
                 }
+                float *hp = hbuf + (static_cast<int64_t>(rr) * bw + hc) * C;
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    hp[ch] = h[ch];
             }
-            float *hp = hbuf + (static_cast<int64_t>(r) * bw + hc) * C;
+        } else {
+            for (int32_t rr = threadIdx.y; rr < wh; rr += bh) {
+                const unsigned char *wrow = win + static_cast<int64_t>(rr) * win_w * PB;
+                float h[C], p[C];
+                Pix<T, C>::load(wrow, hx0, p);
+                fma_first(h, hwx[0], p);
+                for (int32_t k = 1; k < hnx; ++k) {
+                    Pix<T, C>::load(wrow, hx0 + k, p);
+                    fma_next(h, hwx[k], p);
+                }
+                float *hp = hbuf + (static_cast<int64_t>(rr) * bw + hc) * C;
 #pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                hp[ch] = h[ch];
-        }
-    } else {
-        for (int32_t r = threadIdx.y; r < wh; r += bh) {
-            const unsigned char *wrow = win + static_cast<int64_t>(r) * win_w * PB;
-            float h[C], p[C];
-            Pix<T, C>::load(wrow, hx0, p);
-            fma_first(h, hwx[0], p);
-            for (int32_t k = 1; k < hnx; ++k) {
-                Pix<T, C>::load(wrow, hx0 + k, p);
-                fma_next(h, hwx[k], p);
+                for (int ch = 0; ch < C; ++ch)
+                    hp[ch] = h[ch];
             }
-            float *hp = hbuf + (static_cast<int64_t>(r) * bw + hc) * C;
-#pragma unroll
-            for (int ch = 0; ch < C; ++ch)
-                hp[ch] = h[ch];
         }
-    }
-    __syncthreads();
-    const int32_t px = blockIdx.x * bw + threadIdx.x;
-    const int32_t py = blockIdx.y * bh + threadIdx.y;
-    if (px >= a.out_w || py >= a.dst_rows)
-        return;
-    const int32_t r0 = ylo[threadIdx.y] - wy0, ny = yn[threadIdx.y];
-    const float *wyr = yw + threadIdx.y * ky;
-    float acc[C], h[C];
-    for (int32_t j = 0; j < ny; ++j) {
-        const float *hp = hbuf + (static_cast<int64_t>(r0 + j) * bw + threadIdx.x) * C;
+        __syncthreads();
+        const int32_t px = blockIdx.x * bw + threadIdx.x;
+        const int32_t py = by * bh + threadIdx.y;
+        if (px < a.out_w && py < a.dst_rows) {
+            const int32_t r0 = ylo[threadIdx.y] - wy0, ny = yn[threadIdx.y];
+            const float *wyr = yw + threadIdx.y * ky;
+            float acc[C], h[C];
+            for (int32_t j = 0; j < ny; ++j) {
+                const float *hp = hbuf + (static_cast<int64_t>(r0 + j) * bw + threadIdx.x) * C;
 #pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            h[ch] = hp[ch];
-        if (j == 0)
-            fma_first(acc, wyr[0], h);
-        else
-            fma_next(acc, wyr[j], h);
+                for (int ch = 0; ch < C; ++ch)
+                    h[ch] = hp[ch];
+                if (j == 0)
+                    fma_first(acc, wyr[0], h);
+                else
+                    fma_next(acc, wyr[j], h);
+            }
+            unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                                 static_cast<int64_t>(py) * a.dst_pitch;
+            Pix<T, C>::store(dst, px, acc);
+        }
+        // the next tile rewrites the row tables, the window and the row buffer
+        __syncthreads();
     }
-    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
-                         static_cast<int64_t>(py) * a.dst_pitch;
-    Pix<T, C>::store(dst, px, acc);
 }
 
 // Any scale: a thread owns PPX adjacent output columns (each with its own
@@ -1492,8 +1506,16 @@ hipError_t launch_aa_typed(const ResizeArgs &a, const xr_tile &tile, hipStream_t
     } else {
         const AaPlan plan = aa_tile_plan(a.in_w, a.in_h, a.out_w, a.out_h, R, tile.block_w, tile.block_h,
                                          Pix<T, C>::kBytes, C);
-        hipLaunchKernelGGL((k_tile_aa<R, T, C>), grid, block, plan.lds_bytes, stream, a, plan.kx, plan.ky,
-                           plan.win_w, plan.win_h);
+        // tiles per workgroup down a tile column: the column tables are then
+        // built once per tpb tiles, while the grid keeps kAaMinBlocks
+        // workgroups
+        const int64_t cols = static_cast<int64_t>(grid.x) * grid.z;
+        int32_t tpb = 1;
+        while (tpb < kAaTilesPerBlock && cols * ((grid.y + 2 * tpb - 1) / (2 * tpb)) >= kAaMinBlocks)
+            tpb *= 2;
+        const dim3 grid_t(grid.x, (grid.y + tpb - 1) / tpb, grid.z);
+        hipLaunchKernelGGL((k_tile_aa<R, T, C>), grid_t, block, plan.lds_bytes, stream, a, plan.kx, plan.ky,
+                           plan.win_w, plan.win_h, tpb);
     }
     return hipGetLastError();
 }
