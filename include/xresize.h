@@ -175,8 +175,9 @@ int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *t
  *            in a block of block_w x block_h threads (ppt 1 x 1, order 0):
  *            XR_KERNEL_GATHER reads every tap from global memory;
  *            XR_KERNEL_STRIP_LDS stages the block's source window in LDS and
- *            filters it separably (rows, then columns). Both give identical
- *            bits. Strip kinds (and XR_KERNEL_AUTO before tuning) take the
+ *            filters it separably (rows, then columns); when the grid holds
+ *            enough workgroups, one takes up to 4 tiles down its column. Both
+ *            give identical bits. Strip kinds (and XR_KERNEL_AUTO before tuning) take the
  *            first LDS block of 64x4, 64x2, 32x2, 16x2 that fits, else a 64x4
  *            gather. XR_ERR_ARG when the workgroup's LDS exceeds 96 KiB: the
  *            weight tables, 4 (2 bw + 2 bh + bw kx + bh ky) bytes with
