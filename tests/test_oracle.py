@@ -614,3 +614,162 @@ def test_pins_catch_transposed_axes():
         for i in range(4):
             got += (wy[:, j][:, None] * wx[:, i][None, :]) * src[np.clip(iy[:, j], 0, 6)][:, np.clip(ix[:, i], 0, 8)]
     assert np.abs(got - exact).max() > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# the exact single-value evaluator (oracle/exact.py) and the error scale
+# (absolute=True) of the float64 oracle
+# ---------------------------------------------------------------------------
+
+from oracle import exact as EX  # noqa: E402
+
+
+def _abs_brute(img2d, out_h, out_w, filt, a=Fraction(-1, 2)):
+    """sum over every integer sample position i, j of |K(s_y - i)| |K(s_x - j)|
+    |v[clamp(i)][clamp(j)]| (all-taps form, no tap selection, exact): the
+    float32 rounding-error scale of a tap-by-tap evaluation, including the
+    clamped duplicate taps at the edges, which are not merged."""
+    in_h, in_w = len(img2d), len(img2d[0])
+
+    def taps(x, n_in, n_out):
+        s = Fraction((2 * x + 1) * n_in - n_out, 2 * n_out)
+        lo = int(s) - 6
+        return [(min(max(i, 0), n_in - 1), abs(_kernel_exact(s - i, filt, a))) for i in range(lo, lo + 13)
+                if _kernel_exact(s - i, filt, a) != 0]
+
+    out = []
+    for y in range(out_h):
+        row = []
+        for x in range(out_w):
+            v = Fraction(0)
+            for r, wy in taps(y, in_h, out_h):
+                for c, wx in taps(x, in_w, out_w):
+                    v += wy * wx * abs(Fraction(float(img2d[r][c])))
+            row.append(v)
+        out.append(row)
+    return out
+
+
+def _signed_img(h, w, seed):
+    """Signed samples that are exact in float64 (multiples of 1/8)."""
+    rng = np.random.default_rng(seed)
+    return np.round(rng.normal(0.0, 4.0, (h, w)) * 8) / 8
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_exact_values_match_brute_force(shape, filt):
+    in_h, in_w, out_h, out_w = shape
+    img = fields.uniform_u8((in_h, in_w), seed=in_h * 31 + in_w)
+    want = _brute_resize(img.tolist(), out_h, out_w, filt)
+    planes = img[None, :, :, None]
+    for y in range(out_h):
+        for x in range(out_w):
+            assert EX.value(planes, out_h, out_w, filt, 0, y, x, 0) == want[y][x]
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
+@pytest.mark.parametrize("shape", SHAPES[2:6])
+def test_exact_values_match_brute_force_corner_map(shape, filt):
+    in_h, in_w, out_h, out_w = shape
+    img = fields.uniform_u8((in_h, in_w), seed=in_h * 37 + in_w)
+    want = _brute_resize(img.tolist(), out_h, out_w, filt, corner=True)
+    planes = img[None, :, :, None]
+    for y in range(out_h):
+        for x in range(out_w):
+            assert EX.value(planes, out_h, out_w, filt, 0, y, x, 0, mapping=EX.CORNER) == want[y][x]
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR_AA, R.BICUBIC_AA])
+@pytest.mark.parametrize("sizes", [(20, 17, 7, 5), (9, 12, 13, 4), (16, 16, 4, 4)])
+def test_exact_antialiased_values(filt, sizes):
+    """Exact antialiased values: against a brute force over every source
+    index of the image (weight K((i - s) / sigma) when |i - s| < R sigma,
+    then divided by the sum), and against the float64 oracle."""
+    in_h, in_w, out_h, out_w = sizes
+    img = fields.uniform_u8((in_h, in_w), seed=in_h + 5 * in_w)
+    r = 1 if filt == R.BILINEAR_AA else 2
+    base = R.BILINEAR if filt == R.BILINEAR_AA else R.BICUBIC
+
+    def weights(x, n_in, n_out):
+        s = Fraction((2 * x + 1) * n_in - n_out, 2 * n_out)
+        sig = max(Fraction(n_in, n_out), Fraction(1))
+        ws = [(i, _kernel_exact((i - s) / sig, base, Fraction(-1, 2))) for i in range(n_in)
+              if abs(i - s) < r * sig]
+        tot = sum(w for _, w in ws)
+        return [(i, w / tot) for i, w in ws]
+
+    planes = img[None, :, :, None]
+    f64 = R.resize_antialiased(planes, out_h, out_w, filt)[0, :, :, 0]
+    for y in range(out_h):
+        wy = weights(y, in_h, out_h)
+        for x in range(out_w):
+            wx = weights(x, in_w, out_w)
+            want = sum(a * b * int(img[i, j]) for i, a in wy for j, b in wx)
+            got = EX.value(planes, out_h, out_w, filt, 0, y, x, 0)
+            assert got == want
+            assert abs(float(got) - f64[y, x]) <= 1e-12 * max(1.0, abs(f64[y, x]))
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_absolute_scale_pin(shape, filt):
+    """resize_rows(absolute=True) and exact.abs_scale against the all-taps
+    brute force over |w_y| |w_x| |v| on signed data (negative Keys lobes and
+    negative samples make any dropped absolute value visible)."""
+    in_h, in_w, out_h, out_w = shape
+    img = _signed_img(in_h, in_w, seed=in_h * 7 + in_w)
+    want = _abs_brute(img.tolist(), out_h, out_w, filt)
+    planes = img[None, :, :, None]
+    got = R.resize_rows(planes, out_h, out_w, np.arange(out_h), filt, absolute=True)[0, :, :, 0]
+    plain = R.resize_rows(planes, out_h, out_w, np.arange(out_h), filt)[0, :, :, 0]
+    for y in range(out_h):
+        for x in range(out_w):
+            w = float(want[y][x])
+            assert abs(got[y, x] - w) <= 1e-13 * max(1.0, w)
+            assert EX.abs_scale(planes, out_h, out_w, filt, 0, y, x, 0) == want[y][x]
+            assert abs(plain[y, x]) <= got[y, x] * (1 + 1e-13) + 1e-300
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR_AA, R.BICUBIC_AA])
+def test_absolute_scale_pin_antialiased(filt):
+    in_h, in_w, out_h, out_w = 19, 23, 6, 9
+    img = _signed_img(in_h, in_w, seed=11)
+    planes = img[None, :, :, None]
+    got = R.resize_antialiased(planes, out_h, out_w, filt, absolute=True)[0, :, :, 0]
+    for y in range(out_h):
+        ty = EX.axis_taps(y, in_h, out_h, filt)
+        for x in range(out_w):
+            tx = EX.axis_taps(x, in_w, out_w, filt)
+            want = sum(abs(a) * abs(b) * abs(Fraction(float(img[i, j]))) for i, a in ty for j, b in tx)
+            assert abs(got[y, x] - float(want)) <= 1e-12 * float(want)
+            assert EX.abs_scale(planes, out_h, out_w, filt, 0, y, x, 0) == want
+
+
+@pytest.mark.parametrize("filt", [R.BILINEAR, R.BICUBIC])
+@pytest.mark.parametrize("shape", SHAPES[:5])
+def test_absolute_scale_pin_adjoint(shape, filt):
+    """adjoint(absolute=True) against a brute force that scatters
+    |K(s_y - i)| |K(s_x - j)| |g| from every output onto clamp(i), clamp(j)."""
+    in_h, in_w, out_h, out_w = shape
+    g = _signed_img(out_h, out_w, seed=out_h * 5 + out_w)
+    a = Fraction(-1, 2)
+    gs = [[Fraction(0)] * in_w for _ in range(in_h)]
+    for y in range(out_h):
+        sy = Fraction((2 * y + 1) * in_h - out_h, 2 * out_h)
+        for x in range(out_w):
+            sx = Fraction((2 * x + 1) * in_w - out_w, 2 * out_w)
+            gv = abs(Fraction(float(g[y, x])))
+            for i in range(int(sy) - 6, int(sy) + 7):
+                wy = abs(_kernel_exact(sy - i, filt, a))
+                if not wy:
+                    continue
+                for j in range(int(sx) - 6, int(sx) + 7):
+                    wx = abs(_kernel_exact(sx - j, filt, a))
+                    if wx:
+                        gs[min(max(i, 0), in_h - 1)][min(max(j, 0), in_w - 1)] += wy * wx * gv
+    got = R.adjoint(g[None, :, :, None], in_h, in_w, filt, absolute=True)[0, :, :, 0]
+    for r in range(in_h):
+        for c in range(in_w):
+            w = float(gs[r][c])
+            assert abs(got[r, c] - w) <= 1e-13 * max(1.0, w)
