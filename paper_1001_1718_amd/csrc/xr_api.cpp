@@ -248,7 +248,13 @@ int32_t axis_mode(const xr_image &src, const xr_image &dst, const xr_tile &t, in
     if (t.kernel != XR_KERNEL_STRIP || mapping != XR_MAP_HALF_PIXEL || filter == XR_NEAREST ||
         is_aa(filter))
         return xr::kGeneral;
-    if (dst.width == 2 * src.width && dst.height == 2 * src.height)
+    // the x2 walk moves whole dwords through buffer resources: 4-byte aligned
+    // images and pitches
+    const auto al4 = [](const xr_image &im) {
+        return reinterpret_cast<uintptr_t>(im.data) % 4 == 0 && im.row_pitch % 4 == 0 &&
+               (im.planes == 1 || im.plane_pitch % 4 == 0);
+    };
+    if (dst.width == 2 * src.width && dst.height == 2 * src.height && al4(src) && al4(dst))
         return xr::kUp2;
     if (2 * dst.width == src.width && 2 * dst.height == src.height)
         return xr::kDown2;
@@ -285,13 +291,15 @@ std::map<TuneKey, xr_tile> g_tuned;
 
 // Untuned launch shape, by scale (the tuner's typical winners on MI355X):
 //  exact x2     256x1 threads, 4 (RGBA) or 8 (one channel) columns per
-//               thread, strips of 14 rows;
+//               thread, strips of 24 rows (the x2 walk rounds a strip up to
+//               a multiple of 8 rows);
 //  exact x0.5   512x1 threads, 2 or 4 columns, strips of 6 rows;
 //  other        128x2 threads, 2 or 4 columns, strips of 30 rows when the
 //               rows grow, 6 when they shrink (a strip then walks several
 //               source rows per output row).
-// Strips are shortened (14/30 -> 6 -> 2 -> 1 rows) until the launch has about
-// 8 wavefronts per SIMD (2048 x 4); tiny outputs use 64-wide workgroups.
+// Strips are shortened (24/30 -> 16 -> 14 -> 8 -> 6 -> 2 -> 1 rows) until the
+// launch has about 8 wavefronts per SIMD (2048 x 4); tiny outputs use 64-wide
+// workgroups.
 xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w, int32_t rows,
                      int32_t out_h, int32_t planes)
 {
@@ -304,7 +312,7 @@ xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w
         t.block_w = 256;
         t.block_h = 1;
         t.ppt_x = c4 ? 4 : 8;
-        first = 22;  // the tuner's usual choice for large x2 images
+        first = 24;  // the x2 walk's strips of 12 row pairs (measured best on large images)
     } else if (2 * out_w == in_w && 2 * out_h == in_h) {
         t.block_w = 512;
         t.block_h = 1;
@@ -321,7 +329,7 @@ xr_tile default_tile(int32_t channels, int32_t in_w, int32_t in_h, int32_t out_w
         return wcols * ((static_cast<int64_t>(rows) + u.ppt_y - 1) / u.ppt_y) * planes;
     };
     const int64_t target = 8192;
-    const int steps[] = {first, 14, 6, 2, 1};
+    const int steps[] = {first, 16, 14, 8, 6, 2, 1};
     for (int ppy : steps) {
         if (ppy > first)
             continue;
@@ -854,6 +862,23 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     const int ppx_c1[3] = {4, 8, 16};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
     const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}, {256, 2}, {512, 1}};
+    if (out_w == 2 * in_w && out_h == 2 * in_h && filter != XR_NEAREST) {
+        // the exact x2 walk: strips of 8 m rows (m pairs of rows per 4-row
+        // group of its loop), one workgroup order
+        const int x2_rows[] = {8, 16, 24, 32, 48, 64};
+        for (int k = 0; k < 3; ++k) {
+            const int ppx = ppx_list[k];
+            if (!xr::strip_ppx_supported(dtype, channels, ppx))
+                continue;
+            for (const auto &b : blocks)
+                for (int ppy : x2_rows)
+                    c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
+        }
+        if (out)
+            for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)
+                out[k] = c[k];
+        return static_cast<int32_t>(c.size());
+    }
     // strip heights 8m-2 make the x2 walk's source-row groups come out even;
     // 1 and 2 rows give small images enough workgroups
     const int ppy_list[] = {1, 2, 6, 14, 22, 30, 46, 62};

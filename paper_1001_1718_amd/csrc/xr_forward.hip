@@ -10,11 +10,12 @@
 //               rows (the inner sums of eq. 5) are kept in a ring of K
 //               registers and reused by every output row that needs them, so
 //               a source row is filtered once per strip instead of K times.
-//  k_strip_up2  the same walk specialised for an exact x2 upscale on both
-//               axes: output columns/rows alternate between t = 3/4 and
-//               t = 1/4, a thread's ppt_x columns read one contiguous run of
-//               ppt_x/2 + K source pixels with wide loads, and every source
-//               row produces two output rows.
+//  k_x2         the walk specialised for an exact x2 upscale on both axes:
+//               output columns/rows alternate between t = 3/4 and t = 1/4, a
+//               thread's ppt_x columns read one contiguous run of ppt_x/2 + K
+//               source pixels, every source row completes a pair of output
+//               rows, and every memory access goes through a buffer resource
+//               so no branch separates the walk's loads and stores.
 //  k_strip_down2  the walk for an exact x0.5 on both axes: t = 1/2
 //               everywhere, a contiguous run of 2 ppt_x - 2 + K source
 //               pixels per row, two source rows per output row.
@@ -33,6 +34,7 @@
 #include <algorithm>
 #include <type_traits>
 
+#include "xr_buffer.hpp"
 #include "xr_device.hpp"
 #include "xr_internal.h"
 
@@ -866,74 +868,136 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
 }
 
 // ---------------------------------------------------------------------------
-// k_strip_up2 (exact x2 upscale on both axes)
+// k_x2 (exact x2 upscale on both axes)
 // ---------------------------------------------------------------------------
-
-// One thread's walk down its strip. WIDE: the thread's source run and output
-// run lie inside the image and the buffers are 16-byte aligned, so rows move
-// with wide vector loads and stores; otherwise every pixel is loaded from its
-// clamped column and stores are masked at the right edge.
-template <int FILTER, typename T, int C, int PPX, bool WIDE>
-struct Up2Walk {
+//
+// Output rows pair up as (2m+1, 2m+2): both tap the K source rows
+// m+LO .. m+LO+K-1, with t = 1/4 and t = 3/4 (s(y) = (2y - 1)/4). A strip of
+// np pairs (np a multiple of 4) filters np + K - 1 source rows, the first
+// K - 1 before its first pair, and emits both rows of every pair. A thread
+// owns PPX output columns (PPX/2 source columns plus the K/2 taps on either
+// side: a run of SPAN source pixels per row).
+//
+// Every load and store is issued on every step, so the compiler's counts of
+// memory operations in flight are exact and each wait covers only the row it
+// needs (loads run PD rows ahead):
+// * source rows are clamped to the image and the stored band;
+// * output rows outside the caller's band fall outside the store resource
+//   and are dropped;
+// * a thread whose run crosses the left or right image edge loads the run
+//   clamped into the row and rebuilds the edge-replicated pixels in
+//   registers (pixels of 4 bytes or more), or loads each pixel from its
+//   clamped column (1- and 2-byte pixels);
+// * a thread whose output run crosses the right image edge has its run store
+//   dropped (offset moved past the resource) and stores its pixels one by
+//   one.
+// The output stores stream past the L2 (kStoreStream). The float32 operation
+// order per pixel is the one every kernel uses.
+template <int FILTER, typename T, int C, int PPX, int PD>
+struct X2Walk {
     using TP = Taps<FILTER>;
     static constexpr int K = TP::K;
-    static constexpr int M = PPX / 2;   // source columns owned per thread
-    static constexpr int SPAN = M + K;  // source columns read per row
+    static constexpr int LO = TP::LO;
+    static constexpr int M = PPX / 2;
+    static constexpr int SPAN = M + K;
     static constexpr int PB = Pix<T, C>::kBytes;
-    // byte offset of the run start is (M*thread - K/2) * PB
-    static constexpr int RUN_ALIGN = WIDE ? cmin(16, cgcd(M * PB, (K / 2) * PB)) : PB;
-    static constexpr int OUT_ALIGN = cmin(16, PPX * PB);
-    using Raw = RawBuf<SPAN * PB, RUN_ALIGN>;
-
-    const ResizeArgs &a;
-    const unsigned char *src;
-    unsigned char *dst;
-    int32_t col0, run0, y_b, y_e;
-    int32_t r_last;  // last source row an emitted output row reads
-    float we[K], wo[K];
-    // Source row r_first + i sits in ring slot i % K once filtered, and its raw
-    // bytes in queue slot i % Q from the time it is requested (PD rows ahead
-    // of the row being filtered) until it is filtered. The walk is unrolled by
-    // 4 rows, a multiple of K and Q, so every slot index is a constant.
-    static constexpr int PD = (SPAN * PB <= 32) ? 3 : 1;  // prefetch distance in rows
+    // a run starts at source column M t - K/2; loads start MIS bytes lower so
+    // that they begin on a dword (the same MIS for every interior thread)
+    static_assert((M * PB) % 4 == 0, "a thread's run must advance by whole dwords");
+    static constexpr int MIS = (4 - ((K / 2) * PB) % 4) % 4;
+    static constexpr int LB = (MIS + SPAN * PB + 3) / 4 * 4;  // bytes loaded per row
+    static constexpr int OB = PPX * PB;                         // bytes stored per row
     static constexpr int Q = PD + 1;
+    static_assert(4 % K == 0 && 4 % Q == 0, "slots repeat every 4 rows");
+    using Raw = RawBuf<LB, 4>;
+
+    __amdgpu_buffer_rsrc_t srsrc, drsrc;
+    int32_t row_first;   // logical source row of window row 0 of the strip
+    int32_t row_lo, row_hi;  // clamp range (row_lo: the source resource's first row)
+    int64_t src_pitch, dst_pitch;
+    uint32_t lane_src;   // byte offset of this thread's load within a row (dword aligned)
+    int32_t run0, ld0, in_w;  // run: columns run0 .. run0 + SPAN - 1 clamped; edge load at ld0
+    bool edge;
+    uint32_t lane_dst;   // byte offset of this thread's output run (+2^31: dropped)
+    int32_t ncols;       // output columns of this thread inside the image
+    int32_t dst_row_off; // strip row of the store resource's first row
+    float we[K], wo[K];
     float ring[K][PPX][C];
     Raw rawq[Q];
 
-    __device__ __forceinline__ Up2Walk(const ResizeArgs &a_, const unsigned char *s,
-                                       unsigned char *d, int32_t c0, int32_t yb, int32_t ye)
-        : a(a_), src(s), dst(d), col0(c0), run0(c0 / 2 - K / 2), y_b(yb), y_e(ye)
+    __device__ __forceinline__ Raw load_row(int32_t j) const
     {
-        // t = 3/4 on even outputs, 1/4 on odd outputs (s(x) = (2x - 1)/4)
-        weights<FILTER>(0.75f, 0.25f, we);
-        weights<FILTER>(0.25f, 0.75f, wo);
-    }
-
-    // Rows are clamped into the stored band, which holds every row a needed
-    // tap reads (after clamping to the image); rows requested beyond the end
-    // of the walk are therefore valid addresses, merely unused.
-    __device__ __forceinline__ Raw load_row(int32_t r) const
-    {
-        const int32_t rr = clampi(r, a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
-        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
-        if constexpr (WIDE) {
-            return load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
+        const int32_t r = clampi(row_first + j, row_lo, row_hi) - row_lo;
+        const uint32_t roff = static_cast<uint32_t>(static_cast<int64_t>(r) * src_pitch);
+        Raw raw;
+        if constexpr (PB % 4 == 0) {
+            buf_load<LB>(raw.b, srsrc, roff + lane_src);
         } else {
-            Raw raw;
+            if (!edge) {
+                buf_load<LB>(raw.b, srsrc, roff + lane_src);
+            } else {
 #pragma unroll
-            for (int s = 0; s < SPAN; ++s)
-                copy_pixel<PB>(raw.b + s * PB,
-                               row + static_cast<int64_t>(clampi(run0 + s, 0, a.in_w - 1)) * PB);
-            return raw;
+                for (int s = 0; s < SPAN; ++s)
+                    buf_load_px<PB>(raw.b + MIS + s * PB, srsrc,
+                                    roff + static_cast<uint32_t>(clampi(run0 + s, 0, in_w - 1) * PB));
+            }
         }
+        return raw;
     }
 
-    __device__ __forceinline__ void hfilter(const Raw &raw, float (&out)[PPX][C]) const
+    // An edge thread's load holds columns ld0 .. ld0 + SPAN - 1 (ld0 clamped
+    // so the load stays in the row; 0 for images narrower than the run).
+    // Pixel s of its run is column clamp(run0 + s, 0, in_w - 1): first every
+    // loaded pixel past the last column repeats its left neighbour, then the
+    // window moves right by ld0 - run0 pixels repeating its first (left edge)
+    // or left by run0 - ld0 pixels repeating its last (right edge). Lane
+    // values only select, never index, so everything stays in registers.
+    __device__ __forceinline__ Raw clamp_run(const Raw &in) const
     {
+        constexpr int DW = PB / 4;
+        uint32_t w[SPAN][DW];
+        __builtin_memcpy(w, in.b, SPAN * PB);
+        const int32_t last = in_w - 1 - ld0;
+#pragma unroll
+        for (int t = 1; t < SPAN; ++t)
+#pragma unroll
+            for (int d = 0; d < DW; ++d)
+                w[t][d] = t > last ? w[t - 1][d] : w[t][d];
+        const int32_t sh = run0 - ld0;
+#pragma unroll
+        for (int step = 0; step < K / 2; ++step) {
+            const bool go = step < -sh;
+#pragma unroll
+            for (int t = SPAN - 1; t > 0; --t)
+#pragma unroll
+                for (int d = 0; d < DW; ++d)
+                    w[t][d] = go ? w[t - 1][d] : w[t][d];
+        }
+#pragma unroll
+        for (int step = 0; step < M + K / 2; ++step) {
+            const bool go = step < sh;
+#pragma unroll
+            for (int t = 0; t + 1 < SPAN; ++t)
+#pragma unroll
+                for (int d = 0; d < DW; ++d)
+                    w[t][d] = go ? w[t + 1][d] : w[t][d];
+        }
+        Raw out;
+        __builtin_memcpy(out.b, w, SPAN * PB);
+        return out;
+    }
+
+    __device__ __forceinline__ void hfilter(const Raw &loaded, float (&out)[PPX][C]) const
+    {
+        Raw raw = loaded;
+        if constexpr (PB % 4 == 0) {
+            if (edge)
+                raw = clamp_run(loaded);
+        }
         float p[SPAN][C];
 #pragma unroll
         for (int s = 0; s < SPAN; ++s)
-            decode<T, C>(raw.b, s, p[s]);
+            decode<T, C>(raw.b + MIS, s, p[s]);
 #pragma unroll
         for (int q = 0; q < M; ++q) {
             fma_first(out[2 * q], we[0], p[q]);
@@ -947,11 +1011,11 @@ struct Up2Walk {
         }
     }
 
-    // output row y from the window whose oldest row sits in ring slot OLD
+    // strip row `row` (0-based; it may lie outside the band) from the window
+    // whose oldest row sits in ring slot OLD
     template <int OLD>
-    __device__ __forceinline__ void emit(int32_t y, const float (&w)[K])
+    __device__ __forceinline__ void emit_row(int32_t row, const float (&w)[K]) const
     {
-        unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
         float v[PPX][C];
 #pragma unroll
         for (int c = 0; c < PPX; ++c) {
@@ -960,88 +1024,107 @@ struct Up2Walk {
             for (int j = 1; j < K; ++j)
                 fma_next(v[c], w[j], ring[(OLD + j) % K][c]);
         }
-        if constexpr (WIDE) {
-            RawBuf<PPX * PB, OUT_ALIGN> out;
-            encode_run<T, C, PPX>(v, out);
-            store_stream<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
-        } else {
-            const int32_t ncols = min(PPX, a.out_w - col0);
+        RawBuf<OB, cmin(16, OB)> out;
+        encode_run<T, C, PPX>(v, out);
+        const uint32_t roff = static_cast<uint32_t>(static_cast<int64_t>(row - dst_row_off) * dst_pitch);
+        buf_store<OB, kStoreStream>(out.b, drsrc, roff + lane_dst);
+        if (ncols < PPX) {
 #pragma unroll
             for (int c = 0; c < PPX; ++c)
                 if (c < ncols)
-                    Pix<T, C>::store(drow, col0 + c, v[c]);
+                    buf_store<PB, kStoreStream>(out.b + c * PB, drsrc,
+                                                roff + lane_dst - 0x80000000u + static_cast<uint32_t>(c * PB));
         }
     }
 
-    // Filter source row r = r_first + I and emit the two output rows whose
-    // taps are rows r-K+1 .. r: 2r-K+1 (odd, t = 1/4) and 2r-K+2 (even,
-    // t = 3/4). Slots depend on I modulo 4 only. The load of row r + PD is
-    // issued unconditionally, so no branch separates a load from its use and
-    // the wait before filtering covers that one row only.
+    // pair k of the strip: source row k + K - 1 completes its window
     template <int I>
-    __device__ __forceinline__ void step(int32_t r)
+    __device__ __forceinline__ void step(int32_t k, int32_t np)
     {
-        rawq[(I + PD) % Q] = load_row(min(r + PD, r_last));
-        hfilter(rawq[I % Q], ring[I % K]);
-        const int32_t y_odd = 2 * r - K + 1;
-        if (y_odd >= y_b && y_odd < y_e)
-            emit<I + 1>(y_odd, wo);
-        if (y_odd + 1 >= y_b && y_odd + 1 < y_e)
-            emit<I + 1>(y_odd + 1, we);
+        constexpr int J = I + K - 1;  // window row index mod 4
+        rawq[(J + PD) % Q] = load_row(min(k + K - 1 + PD, np + K - 2));
+        __builtin_amdgcn_sched_barrier(0);
+        hfilter(rawq[J % Q], ring[J % K]);
+        emit_row<I>(2 * k, wo);      // row 2m+1, t = 1/4
+        emit_row<I>(2 * k + 1, we);  // row 2m+2, t = 3/4
+        __builtin_amdgcn_sched_barrier(0);
     }
 
-    __device__ __forceinline__ void run()
+    __device__ __forceinline__ void run(int32_t np)
     {
-        // rows r_min .. r_max produce the output rows [y_b, y_e); the walk
-        // runs in groups of 4 rows, so up to 3 rows past r_max are filtered
-        // (copies of row r_max) without emitting anything
-        const int32_t r_min = (y_b + K - 2 + 1) >> 1;  // ceil((y_b + K - 2) / 2), y_b >= 0
-        const int32_t r_max = (y_e - 1 + K - 1) >> 1;  // floor((y_e - 1 + K - 1) / 2)
-        const int32_t r_first = r_min - K + 1;
-        // requests past r_max re-read row r_max (a cache hit) instead of
-        // fetching rows this strip never uses
-        r_last = r_max;
+        weights<FILTER>(0.75f, 0.25f, we);
+        weights<FILTER>(0.25f, 0.75f, wo);
 #pragma unroll
         for (int i = 0; i < PD; ++i)
-            rawq[i % Q] = load_row(min(r_first + i, r_last));
+            rawq[i % Q] = load_row(min(i, np + K - 2));
 #pragma unroll
-        for (int i = 0; i + 1 < K; ++i) {  // rows r_first .. r_min - 1
-            rawq[(i + PD) % Q] = load_row(min(r_first + i + PD, r_last));
-            hfilter(rawq[i % Q], ring[i % K]);
+        for (int j = 0; j + 1 < K; ++j) {
+            rawq[(j + PD) % Q] = load_row(min(j + PD, np + K - 2));
+            hfilter(rawq[j % Q], ring[j % K]);
         }
-        for (int32_t r = r_min; r <= r_max; r += 4) {
-            step<K - 1>(r);
-            step<K>(r + 1);
-            step<K + 1>(r + 2);
-            step<K + 2>(r + 3);
+        // the first four pairs ahead of the loop: the loop's waits then see
+        // the same rows of loads and stores in flight on every iteration
+        step<0>(0, np);
+        step<1>(1, np);
+        step<2>(2, np);
+        step<3>(3, np);
+        for (int32_t k = 4; k < np; k += 4) {
+            step<0>(k, np);
+            step<1>(k + 1, np);
+            step<2>(k + 2, np);
+            step<3>(k + 3, np);
         }
     }
 };
 
+// Rows ahead of use that the x2 walk loads (one row keeps a 4-byte RGBA walk
+// at 98 VGPRs, five wavefronts per SIMD; three rows measured the same)
+constexpr int kX2Prefetch = 1;
+
+// Strip s of np pairs covers logical output rows [2 s np - 1, 2 (s+1) np - 1);
+// threadIdx.y picks one of blockDim.y consecutive strips from s_first on.
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(512) k_strip_up2(ResizeArgs a, int32_t strip_h, int32_t order)
+__global__ void __launch_bounds__(512) k_x2(ResizeArgs a, int32_t np, int32_t s_first)
 {
-    constexpr int K = Taps<FILTER>::K;
-    constexpr int SPAN = PPX / 2 + K;
-    int32_t bx, by;
-    tile_coords(order, bx, by);
-    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + threadIdx.x) * PPX;
-    const int32_t r_begin = strip_begin(by, strip_h);
-    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+    using W = X2Walk<FILTER, T, C, PPX, kX2Prefetch>;
+    constexpr int K = W::K, LO = W::LO, SPAN = W::SPAN, PB = W::PB;
+    const int32_t col0 =
+        (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
+    if (col0 >= a.out_w)
         return;
-    const int32_t run0 = col0 / 2 - K / 2;
-    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
-    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
-    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
-    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
-    const bool wide = a.aligned16 && run0 >= 0 && run0 + SPAN <= a.in_w && col0 + PPX <= a.out_w;
-    if (wide) {
-        Up2Walk<FILTER, T, C, PPX, true> w(a, src, dst, col0, y_b, y_e);
-        w.run();
-    } else {
-        Up2Walk<FILTER, T, C, PPX, false> w(a, src, dst, col0, y_b, y_e);
-        w.run();
-    }
+    const int32_t s =
+        s_first + __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y));
+    const int32_t ys = 2 * s * np - 1;
+    const int32_t y_lo = max(ys, max(a.dst_row0, 0));
+    const int32_t y_hi = min(ys + 2 * np, min(a.dst_row0 + a.dst_rows, a.out_h));
+    if (y_lo >= y_hi)
+        return;
+    W w;
+    // source: the stored band's rows from the strip's first clamped row on
+    const int32_t band_lo = max(0, a.src_row0);
+    const int32_t band_hi = min(a.in_h - 1, a.src_row0 + a.src_rows - 1);
+    w.row_first = s * np - 1 + LO;
+    w.row_lo = clampi(w.row_first, band_lo, band_hi);
+    w.row_hi = clampi(w.row_first + np + K - 2, band_lo, band_hi);  // the strip's last source row
+    w.src_pitch = a.src_pitch;
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch +
+                               static_cast<int64_t>(w.row_lo - a.src_row0) * a.src_pitch;
+    w.srsrc = buf_rsrc(src, static_cast<uint32_t>(static_cast<int64_t>(w.row_hi - w.row_lo) * a.src_pitch +
+                                                  static_cast<int64_t>(a.in_w) * PB));
+    w.run0 = col0 / 2 - K / 2;
+    w.in_w = a.in_w;
+    w.edge = w.run0 < 0 || w.run0 + SPAN > a.in_w;
+    w.ld0 = max(0, min(w.run0, a.in_w - SPAN));
+    w.lane_src = static_cast<uint32_t>((w.edge && PB % 4 == 0) ? w.ld0 * PB : w.run0 * PB - W::MIS);
+    // destination: rows [y_lo, y_hi) of the band
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                         static_cast<int64_t>(y_lo - a.dst_row0) * a.dst_pitch;
+    w.drsrc = buf_rsrc(dst, static_cast<uint32_t>(static_cast<int64_t>(y_hi - y_lo) * a.dst_pitch));
+    w.dst_pitch = a.dst_pitch;
+    w.dst_row_off = y_lo - ys;
+    w.ncols = min(PPX, a.out_w - col0);
+    w.lane_dst = static_cast<uint32_t>(col0 * PB) + (w.ncols < PPX ? 0x80000000u : 0u);
+    w.run(np);
 }
 
 // ---------------------------------------------------------------------------
@@ -1418,6 +1501,36 @@ hipError_t launch_lds(const ResizeArgs &a, const xr_tile &tile, hipStream_t stre
     return hipErrorInvalidValue;
 }
 
+// The x2 walk needs whole-dword runs: (PPX/2) pixels of a thread a multiple
+// of 4 bytes (one-byte pixels: PPX 8 or 16).
+template <typename T, int C, int PPX>
+constexpr bool x2_ppx_ok()
+{
+    return ((PPX / 2) * Pix<T, C>::kBytes) % 4 == 0;
+}
+
+// Strips of 2 np output rows, np = ppt_y / 2 rounded up to a multiple of 4
+// (at least 4), and shortened until a strip's source and output rows stay
+// well inside a buffer resource's 2 GiB.
+template <int FILTER, typename T, int C, int PPX>
+hipError_t launch_x2(const ResizeArgs &a, const xr_tile &tile, hipStream_t stream)
+{
+    int64_t np = std::max<int64_t>(4, (static_cast<int64_t>(tile.ppt_y) + 7) / 8 * 4);
+    const int64_t pitch = std::max(a.src_pitch, a.dst_pitch);
+    while (np > 4 && (2 * np + 8) * pitch >= (int64_t(1) << 30))
+        np -= 4;
+    const int64_t s_first = (static_cast<int64_t>(a.dst_row0) + 1) / (2 * np);
+    const int64_t s_last = (static_cast<int64_t>(a.dst_row0) + a.dst_rows) / (2 * np);
+    const int64_t strips = s_last - s_first + 1;
+    const int32_t cols_per_block = tile.block_w * PPX;
+    const dim3 block(tile.block_w, tile.block_h, 1);
+    const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
+                    static_cast<uint32_t>((strips + tile.block_h - 1) / tile.block_h), a.planes);
+    hipLaunchKernelGGL((k_x2<FILTER, T, C, PPX>), grid, block, 0, stream, a, static_cast<int32_t>(np),
+                       static_cast<int32_t>(s_first));
+    return hipGetLastError();
+}
+
 template <int FILTER, typename T, int C>
 hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, hipStream_t stream)
 {
@@ -1439,9 +1552,8 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
     case P:                                                                                     \
         if constexpr (FILTER != kNearest) {                                                     \
             if (mode == kUp2) {                                                                 \
-                hipLaunchKernelGGL((k_strip_up2<FILTER, T, C, P>), grid, block, 0, stream, a,   \
-                                   tile.ppt_y, tile.order);                                     \
-                return hipGetLastError();                                                       \
+                if constexpr (x2_ppx_ok<T, C, P>())                                             \
+                    return launch_x2<FILTER, T, C, P>(a, tile, stream);                         \
             }                                                                                   \
             if (mode == kDown2) {                                                               \
                 hipLaunchKernelGGL((k_strip_down2<FILTER, T, C, P>), grid, block, 0, stream, a, \
