@@ -862,16 +862,20 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     const int ppx_c1[3] = {4, 8, 16};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
     const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}, {256, 2}, {512, 1}};
-    if (out_w == 2 * in_w && out_h == 2 * in_h && filter != XR_NEAREST) {
+    const bool x2 = out_w == 2 * in_w && out_h == 2 * in_h;
+    const bool x05 = 2 * out_w == in_w && 2 * out_h == in_h;
+    if ((x2 || x05) && filter != XR_NEAREST) {
         // the exact x2 walk: strips of 8 m rows (m pairs of rows per 4-row
-        // group of its loop), one workgroup order
+        // group of its loop); the exact x0.5 walk: strips of an even number
+        // of rows; one workgroup order
         const int x2_rows[] = {8, 16, 24, 32, 48, 64};
+        const int x05_rows[] = {2, 4, 6, 8, 12, 16};
         for (int k = 0; k < 3; ++k) {
             const int ppx = ppx_list[k];
             if (!xr::strip_ppx_supported(dtype, channels, ppx))
                 continue;
             for (const auto &b : blocks)
-                for (int ppy : x2_rows)
+                for (int ppy : (x2 ? x2_rows : x05_rows))
                     c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
         }
         if (out)

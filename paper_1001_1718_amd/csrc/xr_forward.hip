@@ -16,9 +16,10 @@
 //               source pixels, every source row completes a pair of output
 //               rows, and every memory access goes through a buffer resource
 //               so no branch separates the walk's loads and stores.
-//  k_strip_down2  the walk for an exact x0.5 on both axes: t = 1/2
+//  k_x05        the walk for an exact x0.5 on both axes: t = 1/2
 //               everywhere, a contiguous run of 2 ppt_x - 2 + K source
-//               pixels per row, two source rows per output row.
+//               pixels per row, two source rows per output row, with the
+//               buffer-resource loads and stores of k_x2.
 //  k_strip_lds  any scale, each source row staged once per workgroup in LDS.
 //  k_batched    one persistent launch over the tiles of many jobs, each tile
 //               running the k_strip walk of its job.
@@ -868,6 +869,139 @@ __global__ void __launch_bounds__(512) k_strip_lds(ResizeArgs a, int32_t strip_h
 }
 
 // ---------------------------------------------------------------------------
+// output runs of the exact-ratio walks
+// ---------------------------------------------------------------------------
+//
+// A thread's run of PPX output pixels (OB bytes) goes to byte offset
+// row_off + col0 * PB of the store resource (rows outside the resource are
+// dropped by its bound). Runs of up to 16 bytes are stored directly: one
+// store instruction then writes the wavefront's 64 runs as one contiguous
+// span. Wider runs would leave every store instruction writing part of each
+// cache line, which the streaming (past-the-L2) policy turns into partial
+// writes at the memory (float32 RGBA x2: 1.0 ms); they are exchanged through
+// a 64-run LDS area of the wavefront so that store c writes the span's chunks
+// 64 c .. 64 c + 63, whole lines (float32 RGBA x2: 0.19 ms). Pixels past the
+// right image edge are not stored.
+template <typename T, int C, int PPX>
+struct RunStore {
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int OB = PPX * PB;
+    static constexpr bool kExchange = OB > 16;
+    static constexpr int PPC = 16 / PB;  // pixels per 16-byte chunk (exchange)
+
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;       // direct: col0 * PB, + 2^31 when the run crosses the right edge
+    int32_t ncols;           // direct: pixels of the run inside the image
+    unsigned char *xlds;     // exchange: the wavefront's area
+    int32_t lane, wave_col0, out_w;
+
+    // `tid`: the thread's index in its workgroup (blockDim.x a multiple of 64)
+    __device__ __forceinline__ void init(__amdgpu_buffer_rsrc_t r, int32_t col0, int32_t out_w_, int32_t tid,
+                                         unsigned char *lds)
+    {
+        rsrc = r;
+        ncols = max(0, min(PPX, out_w_ - col0));
+        lane_off = static_cast<uint32_t>(col0 * PB) + (ncols < PPX ? 0x80000000u : 0u);
+        lane = tid & 63;
+        xlds = lds + (tid >> 6) * 64 * OB;
+        wave_col0 = col0 - lane * PPX;
+        out_w = out_w_;
+    }
+
+    template <int ALIGN>
+    __device__ __forceinline__ void store(uint32_t row_off, const RawBuf<OB, ALIGN> &out) const
+    {
+        if constexpr (kExchange) {
+            __builtin_memcpy(xlds + lane * OB, out.b, OB);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < OB / 16; ++c) {
+                const int32_t g = lane + 64 * c;
+                const int32_t px = wave_col0 + g * PPC;  // first pixel of chunk g
+                unsigned char chunk[16];
+                __builtin_memcpy(chunk, xlds + 16 * g, 16);
+                const int32_t nv = out_w - px;
+                const uint32_t off = row_off + static_cast<uint32_t>(px * PB);
+                buf_store<16, kStoreStream>(chunk, rsrc, nv >= PPC ? off : off + 0x80000000u);
+                if (nv > 0 && nv < PPC) {
+#pragma unroll
+                    for (int q = 0; q < PPC; ++q)
+                        if (q < nv)
+                            buf_store<PB, kStoreStream>(chunk + q * PB, rsrc, off + static_cast<uint32_t>(q * PB));
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            buf_store<OB, kStoreStream>(out.b, rsrc, row_off + lane_off);
+            if (ncols < PPX) {
+#pragma unroll
+                for (int c = 0; c < PPX; ++c)
+                    if (c < ncols)
+                        buf_store<PB, kStoreStream>(out.b + c * PB, rsrc,
+                                                    row_off + lane_off - 0x80000000u + static_cast<uint32_t>(c * PB));
+            }
+        }
+    }
+};
+
+// LDS bytes of a workgroup of `threads` for RunStore<T, C, PPX>
+template <typename T, int C, int PPX>
+constexpr size_t run_store_lds(int32_t threads)
+{
+    return RunStore<T, C, PPX>::kExchange ? static_cast<size_t>(threads) * RunStore<T, C, PPX>::OB : 0;
+}
+
+// ---------------------------------------------------------------------------
+// edge runs of the exact-ratio walks
+// ---------------------------------------------------------------------------
+//
+// A thread at the image's left or right edge loads its run of N pixels
+// (pixels of a multiple of 4 bytes) from column ld0, clamped so the load stays
+// inside the row (0 for images narrower than the run). Pixel s of the run
+// must be column clamp(run0 + s, 0, in_w - 1): first every loaded pixel past
+// the last column repeats its left neighbour, then the window moves right by
+// ld0 - run0 pixels (at most MAXL) repeating its first pixel, or left by
+// run0 - ld0 (at most MAXR) repeating its last. Lane values only select,
+// never index, so the rebuild stays in registers.
+template <int N, int PB, int MAXL, int MAXR, int LBYTES>
+__device__ __forceinline__ RawBuf<LBYTES, 4> clamp_window(const RawBuf<LBYTES, 4> &in, int32_t run0,
+                                                         int32_t ld0, int32_t in_w)
+{
+    static_assert(PB % 4 == 0 && N * PB <= LBYTES, "whole-dword pixels");
+    constexpr int DW = PB / 4;
+    uint32_t w[N][DW];
+    __builtin_memcpy(w, in.b, N * PB);
+    const int32_t last = in_w - 1 - ld0;
+#pragma unroll
+    for (int t = 1; t < N; ++t)
+#pragma unroll
+        for (int d = 0; d < DW; ++d)
+            w[t][d] = t > last ? w[t - 1][d] : w[t][d];
+    const int32_t sh = run0 - ld0;
+#pragma unroll
+    for (int step = 0; step < MAXL; ++step) {
+        const bool go = step < -sh;
+#pragma unroll
+        for (int t = N - 1; t > 0; --t)
+#pragma unroll
+            for (int d = 0; d < DW; ++d)
+                w[t][d] = go ? w[t - 1][d] : w[t][d];
+    }
+#pragma unroll
+    for (int step = 0; step < MAXR; ++step) {
+        const bool go = step < sh;
+#pragma unroll
+        for (int t = 0; t + 1 < N; ++t)
+#pragma unroll
+            for (int d = 0; d < DW; ++d)
+                w[t][d] = go ? w[t + 1][d] : w[t][d];
+    }
+    RawBuf<LBYTES, 4> out = in;
+    __builtin_memcpy(out.b, w, N * PB);
+    return out;
+}
+
+// ---------------------------------------------------------------------------
 // k_x2 (exact x2 upscale on both axes)
 // ---------------------------------------------------------------------------
 //
@@ -911,15 +1045,14 @@ struct X2Walk {
     static_assert(4 % K == 0 && 4 % Q == 0, "slots repeat every 4 rows");
     using Raw = RawBuf<LB, 4>;
 
-    __amdgpu_buffer_rsrc_t srsrc, drsrc;
+    __amdgpu_buffer_rsrc_t srsrc;
     int32_t row_first;   // logical source row of window row 0 of the strip
     int32_t row_lo, row_hi;  // clamp range (row_lo: the source resource's first row)
     int64_t src_pitch, dst_pitch;
     uint32_t lane_src;   // byte offset of this thread's load within a row (dword aligned)
     int32_t run0, ld0, in_w;  // run: columns run0 .. run0 + SPAN - 1 clamped; edge load at ld0
     bool edge;
-    uint32_t lane_dst;   // byte offset of this thread's output run (+2^31: dropped)
-    int32_t ncols;       // output columns of this thread inside the image
+    RunStore<T, C, PPX> st;
     int32_t dst_row_off; // strip row of the store resource's first row
     float we[K], wo[K];
     float ring[K][PPX][C];
@@ -945,54 +1078,12 @@ struct X2Walk {
         return raw;
     }
 
-    // An edge thread's load holds columns ld0 .. ld0 + SPAN - 1 (ld0 clamped
-    // so the load stays in the row; 0 for images narrower than the run).
-    // Pixel s of its run is column clamp(run0 + s, 0, in_w - 1): first every
-    // loaded pixel past the last column repeats its left neighbour, then the
-    // window moves right by ld0 - run0 pixels repeating its first (left edge)
-    // or left by run0 - ld0 pixels repeating its last (right edge). Lane
-    // values only select, never index, so everything stays in registers.
-    __device__ __forceinline__ Raw clamp_run(const Raw &in) const
-    {
-        constexpr int DW = PB / 4;
-        uint32_t w[SPAN][DW];
-        __builtin_memcpy(w, in.b, SPAN * PB);
-        const int32_t last = in_w - 1 - ld0;
-#pragma unroll
-        for (int t = 1; t < SPAN; ++t)
-#pragma unroll
-            for (int d = 0; d < DW; ++d)
-                w[t][d] = t > last ? w[t - 1][d] : w[t][d];
-        const int32_t sh = run0 - ld0;
-#pragma unroll
-        for (int step = 0; step < K / 2; ++step) {
-            const bool go = step < -sh;
-#pragma unroll
-            for (int t = SPAN - 1; t > 0; --t)
-#pragma unroll
-                for (int d = 0; d < DW; ++d)
-                    w[t][d] = go ? w[t - 1][d] : w[t][d];
-        }
-#pragma unroll
-        for (int step = 0; step < M + K / 2; ++step) {
-            const bool go = step < sh;
-#pragma unroll
-            for (int t = 0; t + 1 < SPAN; ++t)
-#pragma unroll
-                for (int d = 0; d < DW; ++d)
-                    w[t][d] = go ? w[t + 1][d] : w[t][d];
-        }
-        Raw out;
-        __builtin_memcpy(out.b, w, SPAN * PB);
-        return out;
-    }
-
     __device__ __forceinline__ void hfilter(const Raw &loaded, float (&out)[PPX][C]) const
     {
         Raw raw = loaded;
         if constexpr (PB % 4 == 0) {
-            if (edge)
-                raw = clamp_run(loaded);
+            if (edge)  // image edge: rebuild the replicated pixels in registers
+                raw = clamp_window<SPAN, PB, K / 2, M + K / 2>(loaded, run0, ld0, in_w);
         }
         float p[SPAN][C];
 #pragma unroll
@@ -1026,15 +1117,7 @@ struct X2Walk {
         }
         RawBuf<OB, cmin(16, OB)> out;
         encode_run<T, C, PPX>(v, out);
-        const uint32_t roff = static_cast<uint32_t>(static_cast<int64_t>(row - dst_row_off) * dst_pitch);
-        buf_store<OB, kStoreStream>(out.b, drsrc, roff + lane_dst);
-        if (ncols < PPX) {
-#pragma unroll
-            for (int c = 0; c < PPX; ++c)
-                if (c < ncols)
-                    buf_store<PB, kStoreStream>(out.b + c * PB, drsrc,
-                                                roff + lane_dst - 0x80000000u + static_cast<uint32_t>(c * PB));
-        }
+        st.store(static_cast<uint32_t>(static_cast<int64_t>(row - dst_row_off) * dst_pitch), out);
     }
 
     // pair k of the strip: source row k + K - 1 completes its window
@@ -1090,7 +1173,7 @@ __global__ void __launch_bounds__(512) k_x2(ResizeArgs a, int32_t np, int32_t s_
     constexpr int K = W::K, LO = W::LO, SPAN = W::SPAN, PB = W::PB;
     const int32_t col0 =
         (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
-    if (col0 >= a.out_w)
+    if (!RunStore<T, C, PPX>::kExchange && col0 >= a.out_w)  // (an exchange needs every lane)
         return;
     const int32_t s =
         s_first + __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y));
@@ -1119,84 +1202,87 @@ __global__ void __launch_bounds__(512) k_x2(ResizeArgs a, int32_t np, int32_t s_
     // destination: rows [y_lo, y_hi) of the band
     unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
                          static_cast<int64_t>(y_lo - a.dst_row0) * a.dst_pitch;
-    w.drsrc = buf_rsrc(dst, static_cast<uint32_t>(static_cast<int64_t>(y_hi - y_lo) * a.dst_pitch));
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    w.st.init(buf_rsrc(dst, static_cast<uint32_t>(static_cast<int64_t>(y_hi - y_lo) * a.dst_pitch)), col0,
+              a.out_w, static_cast<int32_t>(threadIdx.y * blockDim.x + threadIdx.x), lds);
     w.dst_pitch = a.dst_pitch;
     w.dst_row_off = y_lo - ys;
-    w.ncols = min(PPX, a.out_w - col0);
-    w.lane_dst = static_cast<uint32_t>(col0 * PB) + (w.ncols < PPX ? 0x80000000u : 0u);
     w.run(np);
 }
 
 // ---------------------------------------------------------------------------
-// k_strip_down2 (exact x0.5 on both axes)
+// k_x05 (exact x0.5 on both axes)
 // ---------------------------------------------------------------------------
-
+//
 // For out = in / 2 every output column and row has s = 2x + 1/2: x0 = 2x and
 // t = 1/2, so output x taps source 2x + LO + i with the weights of t = 1/2
 // (bicubic (-1, 9, 9, -1) / 16, bilinear (1/2, 1/2)). A thread's PPX columns
-// read one contiguous run of source pixels; it is loaded from a 16-byte
-// aligned start PAD pixels to the left, so the loads are wide. Every output
-// row reads K source rows starting at 2y + LO: the walk filters two new
-// source rows per output row into a ring of K, unrolled by two output rows
-// (four source rows, a multiple of K and of the prefetch queue) so every
-// slot is a constant. Same float32 evaluation order as the other kernels.
-template <int FILTER, typename T, int C, int PPX, bool WIDE>
-struct Down2Walk {
+// read one run of NEED = 2 PPX - 2 + K source pixels per row; output row y
+// reads the K source rows from 2y + LO on, so a strip of nr output rows (nr
+// even) filters 2 nr + K - 2 source rows, K - 2 before its first output row,
+// into a ring of K, two per output row. Loads and stores are issued on every
+// step, through buffer resources, with the edge rules of k_x2: rows clamped on
+// load, output rows outside the band dropped by the store resource, edge runs
+// rebuilt in registers (or loaded pixel by pixel for 1- and 2-byte pixels),
+// right-edge output runs stored pixel by pixel.
+template <int FILTER, typename T, int C, int PPX, int PD>
+struct D2Walk {
     using TP = Taps<FILTER>;
     static constexpr int K = TP::K;
     static constexpr int LO = TP::LO;
     static constexpr int PB = Pix<T, C>::kBytes;
-    static constexpr int NEED = 2 * PPX - 2 + K;  // source pixels a thread reads per row
-    // alignment of 2 * col0 * PB, capped at 16 bytes
-    static constexpr int RUN_ALIGN = WIDE ? cmin(16, (2 * PPX * PB) & -(2 * PPX * PB)) : PB;
-    static constexpr int U = RUN_ALIGN / PB > 0 ? RUN_ALIGN / PB : 1;  // alignment unit in pixels
-    static constexpr int PAD = WIDE ? ((-LO + U - 1) / U) * U : -LO;   // pixels left of the first tap
-    static constexpr int SPAN = WIDE ? ((PAD + LO + NEED + U - 1) / U) * U : NEED;  // pixels loaded
-    static constexpr int OFF = WIDE ? PAD + LO : 0;  // run index of the first needed pixel
-    static constexpr int OUT_ALIGN = cmin(16, PPX * PB);
-    using Raw = RawBuf<SPAN * PB, WIDE ? RUN_ALIGN : PB>;
-    static constexpr int PD = (SPAN * PB <= 32) ? 3 : 1;  // prefetch distance in rows
+    static constexpr int NEED = 2 * PPX - 2 + K;
+    // a run starts at column 2 col0 + LO; loads start MIS bytes lower, on a dword
+    static_assert((2 * PPX * PB) % 4 == 0, "a thread's run must advance by whole dwords");
+    static constexpr int MIS = (4 - ((-LO) * PB) % 4) % 4;
+    static constexpr int LB = (MIS + NEED * PB + 3) / 4 * 4;
+    static constexpr int OB = PPX * PB;
     static constexpr int Q = PD + 1;
+    static_assert(4 % K == 0 && 4 % Q == 0, "slots repeat every 4 rows");
+    using Raw = RawBuf<LB, 4>;
 
-    const ResizeArgs &a;
-    const unsigned char *src;
-    unsigned char *dst;
-    int32_t col0, run0, y_b, y_e, r_last;
+    __amdgpu_buffer_rsrc_t srsrc;
+    int32_t row_first, row_lo, row_hi;
+    int64_t src_pitch, dst_pitch;
+    uint32_t lane_src;
+    int32_t run0, ld0, in_w, dst_row_off;
+    bool edge;
+    RunStore<T, C, PPX> st;
     float w[K];
     float ring[K][PPX][C];
     Raw rawq[Q];
 
-    __device__ __forceinline__ Down2Walk(const ResizeArgs &a_, const unsigned char *s,
-                                         unsigned char *d, int32_t c0, int32_t yb, int32_t ye)
-        : a(a_), src(s), dst(d), col0(c0), run0(WIDE ? 2 * c0 - PAD : 2 * c0 + LO), y_b(yb), y_e(ye)
+    __device__ __forceinline__ Raw load_row(int32_t j) const
     {
-        weights<FILTER>(0.5f, 0.5f, w);
-    }
-
-    // Rows are clamped into the stored band (which holds every row a needed
-    // tap reads) and to r_last (requests past it re-read that row).
-    __device__ __forceinline__ Raw load_row(int32_t r) const
-    {
-        const int32_t rr = clampi(min(r, r_last), a.src_row0, a.src_row0 + a.src_rows - 1) - a.src_row0;
-        const unsigned char *row = src + static_cast<int64_t>(rr) * a.src_pitch;
-        if constexpr (WIDE) {
-            return load_raw<SPAN * PB, RUN_ALIGN>(row + static_cast<int64_t>(run0) * PB);
+        const int32_t r = clampi(row_first + j, row_lo, row_hi) - row_lo;
+        const uint32_t roff = static_cast<uint32_t>(static_cast<int64_t>(r) * src_pitch);
+        Raw raw;
+        if constexpr (PB % 4 == 0) {
+            buf_load<LB>(raw.b, srsrc, roff + lane_src);
         } else {
-            Raw raw;
+            if (!edge) {
+                buf_load<LB>(raw.b, srsrc, roff + lane_src);
+            } else {
 #pragma unroll
-            for (int s = 0; s < SPAN; ++s)
-                copy_pixel<PB>(raw.b + s * PB,
-                               row + static_cast<int64_t>(clampi(run0 + s, 0, a.in_w - 1)) * PB);
-            return raw;
+                for (int s = 0; s < NEED; ++s)
+                    buf_load_px<PB>(raw.b + MIS + s * PB, srsrc,
+                                    roff + static_cast<uint32_t>(clampi(run0 + s, 0, in_w - 1) * PB));
+            }
         }
+        return raw;
     }
 
-    __device__ __forceinline__ void hfilter(const Raw &raw, float (&out)[PPX][C]) const
+    __device__ __forceinline__ void hfilter(const Raw &loaded, float (&out)[PPX][C]) const
     {
+        Raw raw = loaded;
+        if constexpr (PB % 4 == 0) {
+            if (edge)
+                raw = clamp_window<NEED, PB, -LO, NEED>(loaded, run0, ld0, in_w);
+        }
         float p[NEED][C];
 #pragma unroll
         for (int s = 0; s < NEED; ++s)
-            decode<T, C>(raw.b, OFF + s, p[s]);
+            decode<T, C>(raw.b + MIS, s, p[s]);
 #pragma unroll
         for (int c = 0; c < PPX; ++c) {
             fma_first(out[c], w[0], p[2 * c]);
@@ -1206,11 +1292,10 @@ struct Down2Walk {
         }
     }
 
-    // output row y from the window whose oldest row sits in ring slot OLD
+    // strip row `row` from the window whose oldest row sits in ring slot OLD
     template <int OLD>
-    __device__ __forceinline__ void emit(int32_t y)
+    __device__ __forceinline__ void emit_row(int32_t row) const
     {
-        unsigned char *drow = dst + static_cast<int64_t>(y - a.dst_row0) * a.dst_pitch;
         float v[PPX][C];
 #pragma unroll
         for (int c = 0; c < PPX; ++c) {
@@ -1219,81 +1304,95 @@ struct Down2Walk {
             for (int j = 1; j < K; ++j)
                 fma_next(v[c], w[j], ring[(OLD + j) % K][c]);
         }
-        if constexpr (WIDE) {
-            RawBuf<PPX * PB, OUT_ALIGN> out;
-            encode_run<T, C, PPX>(v, out);
-            store_stream<PPX * PB, OUT_ALIGN>(drow + static_cast<int64_t>(col0) * PB, out);
-        } else {
-            const int32_t ncols = min(PPX, a.out_w - col0);
-#pragma unroll
-            for (int c = 0; c < PPX; ++c)
-                if (c < ncols)
-                    Pix<T, C>::store(drow, col0 + c, v[c]);
-        }
+        RawBuf<OB, cmin(16, OB)> out;
+        encode_run<T, C, PPX>(v, out);
+        st.store(static_cast<uint32_t>(static_cast<int64_t>(row - dst_row_off) * dst_pitch), out);
     }
 
-    // filter source row r_first + I (requesting row r_first + I + PD first)
-    template <int I>
-    __device__ __forceinline__ void filter(int32_t r)
+    // filter window row j (slot J mod K), requesting row j + PD first
+    template <int J>
+    __device__ __forceinline__ void filter(int32_t j, int32_t last)
     {
-        rawq[(I + PD) % Q] = load_row(r + PD);
-        hfilter(rawq[I % Q], ring[I % K]);
+        rawq[(J + PD) % Q] = load_row(min(j + PD, last));
+        __builtin_amdgcn_sched_barrier(0);
+        hfilter(rawq[J % Q], ring[J % K]);
     }
 
-    __device__ __forceinline__ void run()
+    // output row k of the strip: window rows 2k + K - 2 and 2k + K - 1 complete it
+    template <int I>  // k mod 2
+    __device__ __forceinline__ void step(int32_t k, int32_t last)
     {
-        // output y reads source rows 2y + LO .. 2y + LO + K - 1; row
-        // r_first + i sits in ring slot i mod K
-        const int32_t r_first = 2 * y_b + LO;
-        r_last = 2 * (y_e - 1) + LO + K - 1;
+        constexpr int J0 = 2 * I + K - 2;  // window row index mod 4
+        filter<J0>(2 * k + K - 2, last);
+        filter<J0 + 1>(2 * k + K - 1, last);
+        emit_row<2 * I>(k);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    __device__ __forceinline__ void run(int32_t nr)
+    {
+        weights<FILTER>(0.5f, 0.5f, w);
+        const int32_t last = 2 * nr + K - 3;  // the strip's last window row
 #pragma unroll
         for (int i = 0; i < PD; ++i)
-            rawq[i % Q] = load_row(r_first + i);
-        // rows r_first .. r_first + K - 3 come before the first output row's
-        // last two rows
+            rawq[i % Q] = load_row(min(i, last));
         if constexpr (K == 4) {
-            filter<0>(r_first);
-            filter<1>(r_first + 1);
+            filter<0>(0, last);
+            filter<1>(1, last);
         }
-        // output y = y_b + 2m + e completes with source rows
-        // r_first + 4m + 2e + K - 2 and + K - 1
-        constexpr int B = K - 2;  // index of the first row filtered in the loop
-        for (int32_t y = y_b; y < y_e; y += 2) {
-            const int32_t r = r_first + 2 * (y - y_b) + B;
-            filter<B>(r);
-            filter<B + 1>(r + 1);
-            emit<B + 2 - K>(y);
-            filter<B + 2>(r + 2);
-            filter<B + 3>(r + 3);
-            if (y + 1 < y_e)
-                emit<B + 4 - K>(y + 1);
+        step<0>(0, last);
+        step<1>(1, last);
+        for (int32_t k = 2; k < nr; k += 2) {
+            step<0>(k, last);
+            step<1>(k + 1, last);
         }
     }
 };
 
+constexpr int kX05Prefetch = 1;
+
+// Strip s covers logical output rows [s nr, (s + 1) nr); threadIdx.y picks
+// one of blockDim.y consecutive strips from s_first on.
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(512) k_strip_down2(ResizeArgs a, int32_t strip_h, int32_t order)
+__global__ void __launch_bounds__(512) k_x05(ResizeArgs a, int32_t nr, int32_t s_first)
 {
-    using W = Down2Walk<FILTER, T, C, PPX, true>;
-    int32_t bx, by;
-    tile_coords(order, bx, by);
-    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + threadIdx.x) * PPX;
-    const int32_t r_begin = strip_begin(by, strip_h);
-    if (col0 >= a.out_w || r_begin >= a.dst_rows)
+    using W = D2Walk<FILTER, T, C, PPX, kX05Prefetch>;
+    constexpr int K = W::K, LO = W::LO, NEED = W::NEED, PB = W::PB;
+    const int32_t col0 =
+        (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
+    if (!RunStore<T, C, PPX>::kExchange && col0 >= a.out_w)  // (an exchange needs every lane)
         return;
-    const int32_t y_b = a.dst_row0 + r_begin;  // logical rows [y_b, y_e)
-    const int32_t y_e = a.dst_row0 + min(r_begin + strip_h, a.dst_rows);
-    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch;
-    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch;
-    const int32_t run0 = 2 * col0 - W::PAD;
-    const bool wide = a.aligned16 && run0 >= 0 && run0 + W::SPAN <= a.in_w && col0 + PPX <= a.out_w;
-    if (wide) {
-        W w(a, src, dst, col0, y_b, y_e);
-        w.run();
-    } else {
-        Down2Walk<FILTER, T, C, PPX, false> w(a, src, dst, col0, y_b, y_e);
-        w.run();
-    }
+    const int32_t s =
+        s_first + __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y));
+    const int32_t ys = s * nr;
+    const int32_t y_lo = max(ys, max(a.dst_row0, 0));
+    const int32_t y_hi = min(ys + nr, min(a.dst_row0 + a.dst_rows, a.out_h));
+    if (y_lo >= y_hi)
+        return;
+    W w;
+    const int32_t band_lo = max(0, a.src_row0);
+    const int32_t band_hi = min(a.in_h - 1, a.src_row0 + a.src_rows - 1);
+    w.row_first = 2 * ys + LO;
+    w.row_lo = clampi(w.row_first, band_lo, band_hi);
+    w.row_hi = clampi(w.row_first + 2 * nr + K - 3, band_lo, band_hi);
+    w.src_pitch = a.src_pitch;
+    const unsigned char *src = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch +
+                               static_cast<int64_t>(w.row_lo - a.src_row0) * a.src_pitch;
+    w.srsrc = buf_rsrc(src, static_cast<uint32_t>(static_cast<int64_t>(w.row_hi - w.row_lo) * a.src_pitch +
+                                                  static_cast<int64_t>(a.in_w) * PB));
+    w.run0 = 2 * col0 + LO;
+    w.in_w = a.in_w;
+    w.edge = w.run0 < 0 || w.run0 + NEED > a.in_w;
+    w.ld0 = max(0, min(w.run0, a.in_w - NEED));
+    w.lane_src = static_cast<uint32_t>((w.edge && PB % 4 == 0) ? w.ld0 * PB : w.run0 * PB - W::MIS);
+    unsigned char *dst = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                         static_cast<int64_t>(y_lo - a.dst_row0) * a.dst_pitch;
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    w.st.init(buf_rsrc(dst, static_cast<uint32_t>(static_cast<int64_t>(y_hi - y_lo) * a.dst_pitch)), col0,
+              a.out_w, static_cast<int32_t>(threadIdx.y * blockDim.x + threadIdx.x), lds);
+    w.dst_pitch = a.dst_pitch;
+    w.dst_row_off = y_lo - ys;
+    w.run(nr);
 }
 
 // ---------------------------------------------------------------------------
@@ -1503,10 +1602,12 @@ hipError_t launch_lds(const ResizeArgs &a, const xr_tile &tile, hipStream_t stre
 
 // The x2 walk needs whole-dword runs: (PPX/2) pixels of a thread a multiple
 // of 4 bytes (one-byte pixels: PPX 8 or 16).
+// Runs of more than 64 output bytes per thread (float32 RGBA with 8 columns)
+// take the general walk: their rings exceed the register file.
 template <typename T, int C, int PPX>
 constexpr bool x2_ppx_ok()
 {
-    return ((PPX / 2) * Pix<T, C>::kBytes) % 4 == 0;
+    return ((PPX / 2) * Pix<T, C>::kBytes) % 4 == 0 && PPX * Pix<T, C>::kBytes <= 64;
 }
 
 // Strips of 2 np output rows, np = ppt_y / 2 rounded up to a multiple of 4
@@ -1526,8 +1627,29 @@ hipError_t launch_x2(const ResizeArgs &a, const xr_tile &tile, hipStream_t strea
     const dim3 block(tile.block_w, tile.block_h, 1);
     const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
                     static_cast<uint32_t>((strips + tile.block_h - 1) / tile.block_h), a.planes);
-    hipLaunchKernelGGL((k_x2<FILTER, T, C, PPX>), grid, block, 0, stream, a, static_cast<int32_t>(np),
-                       static_cast<int32_t>(s_first));
+    const size_t lds = run_store_lds<T, C, PPX>(tile.block_w * tile.block_h);
+    hipLaunchKernelGGL((k_x2<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(np), static_cast<int32_t>(s_first));
+    return hipGetLastError();
+}
+
+// Strips of nr output rows, nr = ppt_y rounded up to an even count, shortened
+// until a strip's rows stay well inside a buffer resource's 2 GiB.
+template <int FILTER, typename T, int C, int PPX>
+hipError_t launch_x05(const ResizeArgs &a, const xr_tile &tile, hipStream_t stream)
+{
+    int64_t nr = std::max<int64_t>(2, (static_cast<int64_t>(tile.ppt_y) + 1) / 2 * 2);
+    const int64_t pitch = std::max(a.src_pitch, a.dst_pitch);
+    while (nr > 2 && (2 * nr + 8) * pitch >= (int64_t(1) << 30))
+        nr -= 2;
+    const int64_t s_first = static_cast<int64_t>(a.dst_row0) / nr;
+    const int64_t s_last = (static_cast<int64_t>(a.dst_row0) + a.dst_rows - 1) / nr;
+    const int64_t strips = s_last - s_first + 1;
+    const int32_t cols_per_block = tile.block_w * PPX;
+    const dim3 block(tile.block_w, tile.block_h, 1);
+    const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
+                    static_cast<uint32_t>((strips + tile.block_h - 1) / tile.block_h), a.planes);
+    const size_t lds = run_store_lds<T, C, PPX>(tile.block_w * tile.block_h);
+    hipLaunchKernelGGL((k_x05<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(nr), static_cast<int32_t>(s_first));
     return hipGetLastError();
 }
 
@@ -1556,9 +1678,8 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
                     return launch_x2<FILTER, T, C, P>(a, tile, stream);                         \
             }                                                                                   \
             if (mode == kDown2) {                                                               \
-                hipLaunchKernelGGL((k_strip_down2<FILTER, T, C, P>), grid, block, 0, stream, a, \
-                                   tile.ppt_y, tile.order);                                     \
-                return hipGetLastError();                                                       \
+                if constexpr ((2 * P * Pix<T, C>::kBytes) % 4 == 0 && P * Pix<T, C>::kBytes <= 64) \
+                    return launch_x05<FILTER, T, C, P>(a, tile, stream);                        \
             }                                                                                   \
         }                                                                                       \
         hipLaunchKernelGGL((k_strip<FILTER, T, C, P>), grid, block, 0, stream, a, tile.ppt_y,   \

@@ -435,3 +435,34 @@ def test_autotune_choice_does_not_change_results():
     for d in dsts:
         np.testing.assert_array_equal(d.cpu().numpy(), before)
     xr.set_tile("bicubic", xr.XR_U8, 4, 260, 300, 520, 600, xr.tile(xr.XR_KERNEL_AUTO))
+
+
+EXACT_SHAPES = [
+    ((37, 53), (74, 106)),   # x2, ragged
+    ((3, 3), (6, 6)),        # x2, image narrower than one thread's run
+    ((1, 70), (2, 140)),     # x2, one source row
+    ((74, 262), (37, 131)),  # x0.5, ragged
+    ((6, 10), (3, 5)),       # x0.5, narrower than a run
+    ((130, 2), (65, 1)),     # x0.5, one output column
+]
+
+
+@pytest.mark.parametrize("shape", EXACT_SHAPES, ids=lambda s: f"{s[0][0]}x{s[0][1]}-{s[1][0]}x{s[1][1]}")
+@pytest.mark.parametrize("dtype", [np.uint8, np.float16, np.float32], ids=["u8", "f16", "f32"])
+@pytest.mark.parametrize("channels", [1, 4])
+@pytest.mark.parametrize("mode", ["bilinear", "bicubic"])
+def test_exact_ratio_walks_every_width(shape, dtype, channels, mode):
+    """The exact x2 and x0.5 walks with every built run width (direct and
+    LDS-exchanged run stores, edge runs rebuilt in registers or loaded pixel
+    by pixel) and strip heights that split the image unevenly: bitwise equal
+    to each other and to the one-pixel gather, and within the oracle rule."""
+    (in_h, in_w), (out_h, out_w) = shape
+    img = _input(dtype, in_h, in_w, channels, seed=in_h * 31 + in_w * 7 + channels)
+    ref = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_GATHER, 64, 1))
+    compare(ref, img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
+    widths = (2, 4, 8) if channels == 4 else (4, 8, 16)
+    for ppx in widths:
+        for bw, bh, ppy in ((64, 1, 8), (128, 2, 16), (64, 4, 2)):
+            got = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_STRIP, bw, bh, ppx, ppy))
+            np.testing.assert_array_equal(got.view(np.uint8), ref.view(np.uint8),
+                                          err_msg=f"ppx {ppx} block {bw}x{bh} rows {ppy}")
