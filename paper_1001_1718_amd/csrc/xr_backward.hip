@@ -23,6 +23,7 @@
 
 #include <type_traits>
 
+#include "xr_buffer.hpp"
 #include "xr_device.hpp"
 #include "xr_internal.h"
 
@@ -33,16 +34,6 @@ namespace {
 
 constexpr int kBwdThreads = 256;
 
-// N values of T moved as one aligned vector access (ALIGN bytes)
-template <typename T, int N, int ALIGN>
-struct alignas(ALIGN) RawVals {
-    T v[N];
-};
-
-// Alignment of the x2 walk's row runs: they start at (2 c0 + SX0) C sizeof(T)
-// bytes, a multiple of 16 for float32 and of 8 for float16.
-template <typename T>
-constexpr int kRunAlign = sizeof(T) == 4 ? 16 : 8;
 
 // First output index whose clamped taps reach source index >= c, for the
 // axis n_in -> n_out (the map is monotone; see eqs. 1-4).
@@ -226,139 +217,232 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
 // count as zero); k_bwd_up2_border then adds, for the source pixels on the
 // image border, the terms whose taps were clamped onto them.
 
-template <int FILTER, int C, int P>
-struct BwdUp2 {
+
+// The walk: a thread owns P source columns c0 .. c0 + P - 1 and a strip of ns
+// source rows (ns a multiple of 4). Per source row it needs the horizontal
+// adjoints of the 2K output rows 2r - K + 1 .. 2r + K, of which two are new:
+// output rows come in pairs, pair q being rows y_first + 2q and + 1
+// (y_first = 2 r_a - K + 1), held as horizontal adjoints in a ring of 2K rows.
+// A row's window is the W = 2P + 2K - 2 output pixels from column
+// 2 c0 - K + 1 on. Every load and store is issued on every step, through
+// buffer resources: output rows outside the image read as zero (outside the
+// load resource), gradient rows past the strip or the image are dropped
+// (outside the store resource); the first thread of a row loads from column
+// 0 and moves its window right in registers, threads at either edge zero the
+// pixels outside the image. Loads run PD pairs ahead. The float32 order per
+// value is the one the previous register walk used (taps ascending), so the
+// result does not depend on the launch.
+template <int FILTER, typename T, int C, int P, int PD>
+struct BwdX2Walk {
     using TP = Taps<FILTER>;
     static constexpr int K = TP::K;
-    static constexpr int W = 2 * P + 2 * K - 2;       // output pixels read per row
-    static constexpr int SX0 = (C == 1) ? -4 : 1 - K;  // first loaded pixel relative to 2*c0
-    static constexpr int SX = (C == 1) ? 16 : W;       // pixels loaded per row
-    static constexpr int OFF = (1 - K) - SX0;          // window start within the loaded pixels
-    static constexpr int Q = 2;                        // output rows per step
-};
+    static constexpr int W = 2 * P + 2 * K - 2;
+    static constexpr int PB = static_cast<int>(sizeof(T)) * C;
+    static constexpr int MIS = ((K - 1) * PB) % 4;  // the window starts MIS bytes into its first dword
+    static constexpr int LB = (MIS + W * PB + 3) / 4 * 4;
+    static constexpr int Q = PD + 1;
+    static_assert((2 * P * PB) % 4 == 0, "a thread's window must advance by whole dwords");
+    static_assert(4 % Q == 0 && 4 % K == 0, "slots repeat every 4 steps");
+    struct Pair {
+        RawBuf<LB, 4> r[2];
+    };
 
-template <int FILTER, typename T, int C, int P>
-__global__ void __launch_bounds__(256) k_bwd_up2(ResizeArgs a, int32_t strip_h)
-{
-    using B = BwdUp2<FILTER, C, P>;
-    constexpr int K = B::K;
-    constexpr int SX = B::SX;
-    static_assert(C == 4 || P == 4, "one-channel rows are read 16 pixels at a time");
-    float we[K], wo[K];
-    weights<FILTER>(0.75f, 0.25f, we);
-    weights<FILTER>(0.25f, 0.75f, wo);
-    float wt[2 * K];  // transposed weights over the window of one source index
+    __amdgpu_buffer_rsrc_t grsrc;  // upstream rows from y_res on
+    int32_t y_res, y_first;
+    int64_t g_pitch, d_pitch;
+    uint32_t lane_src;
+    int32_t xs, out_w;             // first window column, upstream width
+    bool left, right;              // window starts before column 0 / ends past out_w - 1
+    RunStore<T, C, P> st;
+    int32_t d_row_off;             // strip step of the store resource's first row
+    float wt[2 * K];
+    float ring[2 * K][P][C];
+    Pair rawq[Q];
+
+    __device__ __forceinline__ Pair load_pair(int32_t q) const
+    {
+        Pair pr;
 #pragma unroll
-    for (int q = 0; q < K; ++q) {
-        wt[2 * q] = wo[K - 1 - q];
-        wt[2 * q + 1] = we[K - 1 - q];
+        for (int h = 0; h < 2; ++h) {
+            const int32_t y = y_first + 2 * q + h;
+            const uint32_t roff = static_cast<uint32_t>(static_cast<int64_t>(y - y_res) * g_pitch);
+            buf_load<LB>(pr.r[h].b, grsrc, roff + lane_src);
+        }
+        return pr;
     }
 
-    const int32_t c0 = (blockIdx.x * blockDim.x + threadIdx.x) * P;
-    const int32_t r_a = __builtin_amdgcn_readfirstlane(blockIdx.y * strip_h);
-    if (c0 >= a.in_w || r_a >= a.in_h)
-        return;
-    const int32_t r_b = min(r_a + strip_h, a.in_h);
-    const int32_t plane = blockIdx.z;
-    const unsigned char *gsrc = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch;
-    const int32_t xs = 2 * c0 + B::SX0;  // first loaded output column
-    const bool wide = a.aligned16 && xs >= 0 && xs + SX <= a.out_w && c0 + P <= a.in_w;
-
-    // one output row's pixels [xs, xs + SX), zero outside the image
-    auto load_row = [&](int32_t y, float (&v)[SX][C]) {
-        const bool row_ok = y >= 0 && y < a.out_h;
-        const int32_t yy = clampi(y, 0, a.out_h - 1);
-        const unsigned char *row = gsrc + static_cast<int64_t>(yy) * a.src_pitch;
-        if (wide) {
-            const auto raw = *reinterpret_cast<const RawVals<T, SX * C, kRunAlign<T>> *>(
-                __builtin_assume_aligned(row + static_cast<int64_t>(xs) * C * sizeof(T), kRunAlign<T>));
+    // the window's pixels as floats; at an image edge, pixels outside are zero
+    __device__ __forceinline__ void window(const RawBuf<LB, 4> &raw, float (&v)[W][C]) const
+    {
+        RawBuf<LB, 4> in = raw;
+        if (left) {
+            // loaded from column 0: pixel s of the window is loaded pixel
+            // s + xs, i.e. the bytes move right by -xs pixels (1 .. K - 1)
 #pragma unroll
-            for (int s = 0; s < SX; ++s)
+            for (int n = 1; n < K; ++n) {
+                const int SH = n * PB + MIS;  // bytes
+                RawBuf<LB, 4> sh;
 #pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    v[s][ch] = row_ok ? static_cast<float>(raw.v[s * C + ch]) : 0.0f;
-        } else {
-#pragma unroll
-            for (int s = 0; s < SX; ++s) {
-                const int32_t x = xs + s;
-                const bool ok = row_ok && x >= 0 && x < a.out_w;
-                float p[C];
-                Pix<T, C>::load(row, clampi(x, 0, a.out_w - 1), p);
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    v[s][ch] = ok ? p[ch] : 0.0f;
+                for (int b = 0; b < LB; ++b)
+                    sh.b[b] = b >= SH ? raw.b[b - SH] : 0;
+                if (-xs == n)
+                    in = sh;
             }
         }
-    };
-    // horizontal adjoint of one output row for the P owned source columns
-    auto hadj = [&](const float (&v)[SX][C], float (&u)[P][C]) {
+#pragma unroll
+        for (int s = 0; s < W; ++s) {
+            float p[C];
+            if constexpr (std::is_same_v<T, float>) {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    __builtin_memcpy(&p[ch], in.b + MIS + (s * C + ch) * 4, 4);
+            } else {
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch) {
+                    _Float16 hv;
+                    __builtin_memcpy(&hv, in.b + MIS + (s * C + ch) * 2, 2);
+                    p[ch] = static_cast<float>(hv);
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < C; ++ch)
+                v[s][ch] = p[ch];
+        }
+        if (left || right) {
+#pragma unroll
+            for (int s = 0; s < W; ++s) {
+                const int32_t x = xs + s;
+                const bool ok = x >= 0 && x < out_w;
+#pragma unroll
+                for (int ch = 0; ch < C; ++ch)
+                    v[s][ch] = ok ? v[s][ch] : 0.0f;
+            }
+        }
+    }
+
+    __device__ __forceinline__ void hadj(const RawBuf<LB, 4> &raw, float (&u)[P][C]) const
+    {
+        float v[W][C];
+        window(raw, v);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            fma_first(u[p], wt[0], v[B::OFF + 2 * p]);
+            fma_first(u[p], wt[0], v[2 * p]);
 #pragma unroll
             for (int d = 1; d < 2 * K; ++d)
-                fma_next(u[p], wt[d], v[B::OFF + 2 * p + d]);
+                fma_next(u[p], wt[d], v[2 * p + d]);
         }
-    };
-
-    // ring of the horizontal adjoints of output rows y, slot (y - y_first) mod 2K
-    float ring[2 * K][P][C];
-    const int32_t y_first = 2 * r_a - K + 1;
-    float va[SX][C], vb[SX][C];
-#pragma unroll
-    for (int k = 0; k + 2 < 2 * K; k += 2) {  // rows y_first .. y_first + 2K - 3
-        load_row(y_first + k, va);
-        load_row(y_first + k + 1, vb);
-        hadj(va, ring[k]);
-        hadj(vb, ring[k + 1]);
     }
-    unsigned char *gdst = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch;
-    const int32_t ncols = min(P, a.in_w - c0);
-    auto step = [&](auto slot_tag, int32_t r) {
-        constexpr int S = decltype(slot_tag)::value;  // slot of the first new row
-        // rows 2r + K - 1 and 2r + K complete the window of source row r
-        load_row(2 * r + K - 1, va);
-        load_row(2 * r + K, vb);
-        hadj(va, ring[S % (2 * K)]);
-        hadj(vb, ring[(S + 1) % (2 * K)]);
+
+    // source row r_a + j: pair K - 1 + j completes its window; ring slot of
+    // pair q's first row is 2q mod 2K
+    template <int I>  // j mod 4
+    __device__ __forceinline__ void step(int32_t j, int32_t last_pair)
+    {
+        constexpr int QI = I + K - 1;  // pair index mod 4
+        rawq[(QI + PD) % Q] = load_pair(min(j + K - 1 + PD, last_pair));
+        __builtin_amdgcn_sched_barrier(0);
+        hadj(rawq[QI % Q].r[0], ring[(2 * QI) % (2 * K)]);
+        hadj(rawq[QI % Q].r[1], ring[(2 * QI + 1) % (2 * K)]);
         float g[P][C];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            fma_first(g[p], wt[0], ring[(S + 2) % (2 * K)][p]);
+            fma_first(g[p], wt[0], ring[(2 * I) % (2 * K)][p]);
 #pragma unroll
             for (int d = 1; d < 2 * K; ++d)
-                fma_next(g[p], wt[d], ring[(S + 2 + d) % (2 * K)][p]);
+                fma_next(g[p], wt[d], ring[(2 * I + d) % (2 * K)][p]);
         }
-        unsigned char *drow = gdst + static_cast<int64_t>(r) * a.dst_pitch;
-        if (wide) {
-            RawVals<T, P * C, kRunAlign<T>> out;
+        RawBuf<P * PB, cmin(16, P * PB)> out;
 #pragma unroll
-            for (int p = 0; p < P; ++p)
+        for (int p = 0; p < P; ++p)
 #pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    out.v[p * C + ch] = static_cast<T>(g[p][ch]);
-            *reinterpret_cast<RawVals<T, P * C, kRunAlign<T>> *>(
-                __builtin_assume_aligned(drow + static_cast<int64_t>(c0) * C * sizeof(T), kRunAlign<T>)) = out;
-        } else {
+            for (int ch = 0; ch < C; ++ch) {
+                const T vv = static_cast<T>(g[p][ch]);
+                __builtin_memcpy(out.b + (p * C + ch) * sizeof(T), &vv, sizeof(T));
+            }
+        st.store(static_cast<uint32_t>(static_cast<int64_t>(j - d_row_off) * d_pitch), out);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+    __device__ __forceinline__ void run(int32_t ns)
+    {
+        float we[K], wo[K];
+        weights<FILTER>(0.75f, 0.25f, we);
+        weights<FILTER>(0.25f, 0.75f, wo);
 #pragma unroll
-            for (int p = 0; p < P; ++p)
-                if (p < ncols)
-                    Pix<T, C>::store(drow, c0 + p, g[p]);
+        for (int q = 0; q < K; ++q) {
+            wt[2 * q] = wo[K - 1 - q];
+            wt[2 * q + 1] = we[K - 1 - q];
         }
-    };
-    // the window of row r starts at slot (2(r - r_a)) mod 2K; unroll K rows so
-    // that every slot index is a constant
-    for (int32_t r = r_a; r < r_b; r += K) {
-        step(std::integral_constant<int, 2 * K - 2>{}, r);
-        if (r + 1 < r_b)
-            step(std::integral_constant<int, 2 * K>{}, r + 1);
-        if constexpr (K == 4) {
-            if (r + 2 < r_b)
-                step(std::integral_constant<int, 2 * K + 2>{}, r + 2);
-            if (r + 3 < r_b)
-                step(std::integral_constant<int, 2 * K + 4>{}, r + 3);
+        const int32_t last_pair = ns + K - 2;
+#pragma unroll
+        for (int i = 0; i < PD; ++i)
+            rawq[i % Q] = load_pair(min(i, last_pair));
+#pragma unroll
+        for (int q = 0; q + 1 < K; ++q) {
+            rawq[(q + PD) % Q] = load_pair(min(q + PD, last_pair));
+            hadj(rawq[q % Q].r[0], ring[(2 * q) % (2 * K)]);
+            hadj(rawq[q % Q].r[1], ring[(2 * q + 1) % (2 * K)]);
+        }
+        step<0>(0, last_pair);
+        step<1>(1, last_pair);
+        step<2>(2, last_pair);
+        step<3>(3, last_pair);
+        for (int32_t j = 4; j < ns; j += 4) {
+            step<0>(j, last_pair);
+            step<1>(j + 1, last_pair);
+            step<2>(j + 2, last_pair);
+            step<3>(j + 3, last_pair);
         }
     }
+};
+
+// Pairs of upstream rows loaded ahead of use: one for windows of up to 64
+// bytes per row, none for wider ones (RGBA float32 bicubic: 128 bytes a row;
+// a queue of them would take most of the register file)
+template <typename T, int C, int P, int K>
+constexpr int bwd_x2_prefetch()
+{
+    return (2 * P + 2 * K - 2) * static_cast<int>(sizeof(T)) * C <= 64 ? 1 : 0;
+}
+
+// a.src = grad_dst (out_w x out_h), a.dst = grad_src (in_w x in_h); strip s of
+// ns source rows covers rows [s ns, (s + 1) ns); threadIdx.y picks one of
+// blockDim.y consecutive strips.
+template <int FILTER, typename T, int C, int P>
+__global__ void __launch_bounds__(256) k_bwd_x2(ResizeArgs a, int32_t ns)
+{
+    using Wk = BwdX2Walk<FILTER, T, C, P, bwd_x2_prefetch<T, C, P, Taps<FILTER>::K>()>;
+    constexpr int K = Wk::K, W = Wk::W, PB = Wk::PB;
+    const int32_t c0 = (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * P;
+    if (!RunStore<T, C, P>::kExchange && c0 >= a.in_w)
+        return;
+    const int32_t r_a = __builtin_amdgcn_readfirstlane(
+        static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y) * ns);
+    if (r_a >= a.in_h)
+        return;
+    const int32_t r_b = min(r_a + ns, a.in_h);
+    Wk w;
+    w.y_first = 2 * r_a - K + 1;
+    // upstream rows the strip reads, inside the image
+    w.y_res = max(0, w.y_first);
+    const int32_t y_end = min(a.out_h, 2 * (r_a + ns) + K);
+    w.g_pitch = a.src_pitch;
+    const unsigned char *g = a.src + static_cast<int64_t>(blockIdx.z) * a.src_plane_pitch +
+                             static_cast<int64_t>(w.y_res) * a.src_pitch;
+    w.grsrc = buf_rsrc(g, static_cast<uint32_t>(static_cast<int64_t>(y_end - w.y_res) * a.src_pitch));
+    w.xs = 2 * c0 - K + 1;
+    w.out_w = a.out_w;
+    w.left = w.xs < 0;
+    w.right = w.xs + W > a.out_w;
+    w.lane_src = w.left ? 0u : static_cast<uint32_t>(w.xs * PB - Wk::MIS);
+    unsigned char *d = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
+                       static_cast<int64_t>(r_a) * a.dst_pitch;
+    extern __shared__ __attribute__((aligned(16))) unsigned char xlds[];
+    w.st.init(buf_rsrc(d, static_cast<uint32_t>(static_cast<int64_t>(r_b - r_a) * a.dst_pitch)), c0, a.in_w,
+              static_cast<int32_t>(threadIdx.y * blockDim.x + threadIdx.x), xlds);
+    w.d_pitch = a.dst_pitch;
+    w.d_row_off = 0;
+    w.run(ns);
 }
 
 // Border source pixels: add the terms whose row or column tap was clamped onto
@@ -448,12 +532,16 @@ template <int FILTER, typename T, int C>
 hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
 {
     constexpr int P = (C == 1) ? 4 : 1;
-    constexpr int32_t kStrip = 16;
+    // strips of 16 source rows, shortened so that a strip's rows stay well
+    // inside a buffer resource's 2 GiB
+    int32_t ns = 16;
+    while (ns > 4 && (2 * ns + 8) * std::max(a.src_pitch, a.dst_pitch) >= (int64_t(1) << 30))
+        ns -= 4;
     const int32_t cols_per_block = 256 * P;
-    hipLaunchKernelGGL((k_bwd_up2<FILTER, T, C, P>),
-                       dim3((a.in_w + cols_per_block - 1) / cols_per_block, (a.in_h + kStrip - 1) / kStrip,
-                            a.planes),
-                       dim3(256), 0, stream, a, kStrip);
+    const size_t lds = RunStore<T, C, P>::kExchange ? 256 * RunStore<T, C, P>::OB : 0;
+    hipLaunchKernelGGL((k_bwd_x2<FILTER, T, C, P>),
+                       dim3((a.in_w + cols_per_block - 1) / cols_per_block, (a.in_h + ns - 1) / ns, a.planes),
+                       dim3(256), lds, stream, a, ns);
     const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
     const int32_t border = ((a.in_h > 1) ? 2 * a.in_w : a.in_w) + ((a.in_w > 1) ? 2 * inner : inner);
     hipLaunchKernelGGL((k_bwd_up2_border<FILTER, T, C>), dim3((border + 255) / 256, a.planes), dim3(256), 0,

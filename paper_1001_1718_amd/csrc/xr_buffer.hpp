@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "xr_device.hpp"
+
 namespace xr {
 namespace dev {
 
@@ -91,4 +93,97 @@ __device__ __forceinline__ void buf_store(const unsigned char *src, __amdgpu_buf
 }
 
 }  // namespace dev
+
+// BYTES bytes held in registers (a run of pixels), aligned to ALIGN.
+template <int BYTES, int ALIGN>
+struct alignas(ALIGN) RawBuf {
+    unsigned char b[BYTES];
+};
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+using namespace dev;
+
+// Output runs of the walks.
+//
+// A thread's run of PPX output pixels (OB bytes) goes to byte offset
+// row_off + col0 * PB of the store resource (rows outside the resource are
+// dropped by its bound). Runs of up to 16 bytes are stored directly: one
+// store instruction then writes the wavefront's 64 runs as one contiguous
+// span. Wider runs would leave every store instruction writing part of each
+// cache line, which the streaming (past-the-L2) policy turns into partial
+// writes at the memory (float32 RGBA x2: 1.0 ms); they are exchanged through
+// a 64-run LDS area of the wavefront so that store c writes the span's chunks
+// 64 c .. 64 c + 63, whole lines (float32 RGBA x2: 0.19 ms). Pixels past the
+// right image edge are not stored.
+template <typename T, int C, int PPX>
+struct RunStore {
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int OB = PPX * PB;
+    static constexpr bool kExchange = OB > 16;
+    static constexpr int PPC = 16 / PB;  // pixels per 16-byte chunk (exchange)
+
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;       // direct: col0 * PB, + 2^31 when the run crosses the right edge
+    int32_t ncols;           // direct: pixels of the run inside the image
+    unsigned char *xlds;     // exchange: the wavefront's area
+    int32_t lane, wave_col0, out_w;
+
+    // `tid`: the thread's index in its workgroup (blockDim.x a multiple of 64)
+    __device__ __forceinline__ void init(__amdgpu_buffer_rsrc_t r, int32_t col0, int32_t out_w_, int32_t tid,
+                                         unsigned char *lds)
+    {
+        rsrc = r;
+        ncols = max(0, min(PPX, out_w_ - col0));
+        lane_off = static_cast<uint32_t>(col0 * PB) + (ncols < PPX ? 0x80000000u : 0u);
+        lane = tid & 63;
+        xlds = lds + (tid >> 6) * 64 * OB;
+        wave_col0 = col0 - lane * PPX;
+        out_w = out_w_;
+    }
+
+    template <int ALIGN>
+    __device__ __forceinline__ void store(uint32_t row_off, const RawBuf<OB, ALIGN> &out) const
+    {
+        if constexpr (kExchange) {
+            __builtin_memcpy(xlds + lane * OB, out.b, OB);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = 0; c < OB / 16; ++c) {
+                const int32_t g = lane + 64 * c;
+                const int32_t px = wave_col0 + g * PPC;  // first pixel of chunk g
+                unsigned char chunk[16];
+                __builtin_memcpy(chunk, xlds + 16 * g, 16);
+                const int32_t nv = out_w - px;
+                const uint32_t off = row_off + static_cast<uint32_t>(px * PB);
+                buf_store<16, kStoreStream>(chunk, rsrc, nv >= PPC ? off : off + 0x80000000u);
+                if (nv > 0 && nv < PPC) {
+#pragma unroll
+                    for (int q = 0; q < PPC; ++q)
+                        if (q < nv)
+                            buf_store<PB, kStoreStream>(chunk + q * PB, rsrc, off + static_cast<uint32_t>(q * PB));
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            buf_store<OB, kStoreStream>(out.b, rsrc, row_off + lane_off);
+            if (ncols < PPX) {
+#pragma unroll
+                for (int c = 0; c < PPX; ++c)
+                    if (c < ncols)
+                        buf_store<PB, kStoreStream>(out.b + c * PB, rsrc,
+                                                    row_off + lane_off - 0x80000000u + static_cast<uint32_t>(c * PB));
+            }
+        }
+    }
+};
+
+// LDS bytes of a workgroup of `threads` for RunStore<T, C, PPX>
+template <typename T, int C, int PPX>
+constexpr size_t run_store_lds(int32_t threads)
+{
+    return RunStore<T, C, PPX>::kExchange ? static_cast<size_t>(threads) * RunStore<T, C, PPX>::OB : 0;
+}
+
 }  // namespace xr
