@@ -18,7 +18,7 @@
 //
 // Every sum has a fixed order, so the result is deterministic (bit for bit
 // the same on every run and for every tiling of the launch). The exact-x2
-// path below (float32 and float16) is deterministic as well.
+// walk below (float32 and float16) is deterministic as well.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -213,18 +213,20 @@ __global__ void __launch_bounds__(kBwdThreads) k_bwd_owner(ResizeArgs a, int32_t
 // (t = 3/4) and lo(2m+1) = m + LO (t = 1/4). Ignoring the clamp, source
 // column c therefore receives the 2K outputs x = 2c - K + 1 + d, d = 0..2K-1,
 // with weight wo[K-1-q] for d = 2q and we[K-1-q] for d = 2q+1; rows alike.
-// k_bwd_up2 sums exactly those unclamped terms (outputs outside the image
-// count as zero); k_bwd_up2_border then adds, for the source pixels on the
-// image border, the terms whose taps were clamped onto them.
-
-
+// k_bwd_x2 sums exactly those unclamped terms (outputs outside the image
+// count as zero), and the threads that own the image's first or last row or
+// column add the terms whose taps were clamped onto them, so every gradient
+// is one sum rounded once.
+//
 // The walk: a thread owns P source columns c0 .. c0 + P - 1 and a strip of ns
 // source rows (ns a multiple of 4). Per source row it needs the horizontal
 // adjoints of the 2K output rows 2r - K + 1 .. 2r + K, of which two are new:
 // output rows come in pairs, pair q being rows y_first + 2q and + 1
 // (y_first = 2 r_a - K + 1), held as horizontal adjoints in a ring of 2K rows.
 // A row's window is the W = 2P + 2K - 2 output pixels from column
-// 2 c0 - K + 1 on. Every load and store is issued on every step, through
+// 2 c0 - K + 1 on; these sums leave out the taps that were clamped onto the
+// image's first or last row or column, which the threads owning those pixels
+// add on their own (see `clamped`). Every load and store is issued on every step, through
 // buffer resources: output rows outside the image read as zero (outside the
 // load resource), gradient rows past the strip or the image are dropped
 // (outside the store resource); the first thread of a row loads from column
@@ -253,6 +255,13 @@ struct BwdX2Walk {
     uint32_t lane_src;
     int32_t xs, out_w;             // first window column, upstream width
     bool left, right;              // window starts before column 0 / ends past out_w - 1
+    bool own_first;                // this thread owns column 0
+    int32_t p_right;               // owned column index of column in_w - 1, or -1
+    int32_t r_a, in_h;
+    // clamped taps (see `clamped`): summed weight of the taps of output index
+    // m (m = 0 .. K - 1 from the first, resp. last, output on) that land
+    // before column / row 0, resp. past the last one
+    float wlo[K], whi[K];
     RunStore<T, C, P> st;
     int32_t d_row_off;             // strip step of the store resource's first row
     float wt[2 * K];
@@ -331,6 +340,27 @@ struct BwdX2Walk {
             for (int d = 1; d < 2 * K; ++d)
                 fma_next(u[p], wt[d], v[2 * p + d]);
         }
+        if (own_first) {
+            // column 0 (this thread's first, c0 = 0, window from column
+            // 1 - K): taps clamped from the left; output column m is window
+            // pixel m + K - 1
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+                fma_next(u[0], wlo[m], v[m + K - 1]);
+        }
+        if (p_right >= 0) {
+            // column in_w - 1 = c0 + p_right: taps clamped from the right.
+            // With c0 = in_w - 1 - p_right the window starts at column
+            // out_w - 1 - K - 2 p_right, so output column out_w - K + m is
+            // window pixel m + 1 + 2 p_right.
+#pragma unroll
+            for (int pr = 0; pr < P; ++pr)
+                if (p_right == pr) {
+#pragma unroll
+                    for (int m = 0; m < K; ++m)
+                        fma_next(u[pr], whi[m], v[m + 1 + 2 * pr]);
+                }
+        }
     }
 
     // source row r_a + j: pair K - 1 + j completes its window; ring slot of
@@ -351,6 +381,26 @@ struct BwdX2Walk {
             for (int d = 1; d < 2 * K; ++d)
                 fma_next(g[p], wt[d], ring[(2 * I + d) % (2 * K)][p]);
         }
+        const int32_t r = r_a + j;
+        if (r == 0) {
+            // taps of output rows 0 .. K - 1 clamped onto row 0; output row m
+            // sits at window row m + K - 1 (2j + K - 1 + m, j = 0 here)
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    fma_next(g[p], wlo[m], ring[(2 * I + K - 1 + m) % (2 * K)][p]);
+        }
+        if (r == in_h - 1) {
+            // taps of output rows out_h - K + m clamped onto the last row;
+            // this step's window starts at output row 2r - K + 1, so output
+            // row 2 in_h - K + m is its window row m + 1
+#pragma unroll
+            for (int m = 0; m < K; ++m)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    fma_next(g[p], whi[m], ring[(2 * I + 1 + m) % (2 * K)][p]);
+        }
         RawBuf<P * PB, cmin(16, P * PB)> out;
 #pragma unroll
         for (int p = 0; p < P; ++p)
@@ -363,6 +413,44 @@ struct BwdX2Walk {
         __builtin_amdgcn_sched_barrier(0);
     }
 
+    // Taps clamped onto the first or last source index of an axis (the same
+    // on both axes at x2): output m (m = 0 .. K - 1) has x0 = floor((2m - 1)/4)
+    // with t = 3/4 (even m) or 1/4 (odd m); its taps x0 + LO + i below 0 land
+    // on index 0. Mirrored, output n - K + m has taps past n_in - 1 where
+    // output K - 1 - m has them below 0, with the weights reversed.
+    __device__ __forceinline__ void clamped()
+    {
+        float we[K], wo[K];
+        weights<FILTER>(0.75f, 0.25f, we);
+        weights<FILTER>(0.25f, 0.75f, wo);
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const int x0 = (m % 2 == 0) ? m / 2 - 1 : (m - 1) / 2;
+            const float *w = (m % 2 == 0) ? we : wo;
+            float lo = 0.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (x0 + TP::LO + i < 0)
+                    lo += w[i];
+            wlo[m] = lo;
+        }
+        // output n - K + m mirrors output K - 1 - m (the map and the kernel are
+        // symmetric about the axis centre), so its taps past the end carry the
+        // same weights; their sum is exact in float32 (dyadic weights)
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+            const int mm = K - 1 - m;
+            const int x0 = (mm % 2 == 0) ? mm / 2 - 1 : (mm - 1) / 2;
+            const float *w = (mm % 2 == 0) ? we : wo;
+            float hi = 0.0f;
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                if (x0 + TP::LO + i < 0)
+                    hi += w[i];
+            whi[m] = hi;
+        }
+    }
+
     __device__ __forceinline__ void run(int32_t ns)
     {
         float we[K], wo[K];
@@ -373,6 +461,7 @@ struct BwdX2Walk {
             wt[2 * q] = wo[K - 1 - q];
             wt[2 * q + 1] = we[K - 1 - q];
         }
+        clamped();
         const int32_t last_pair = ns + K - 2;
 #pragma unroll
         for (int i = 0; i < PD; ++i)
@@ -435,6 +524,10 @@ __global__ void __launch_bounds__(256) k_bwd_x2(ResizeArgs a, int32_t ns)
     w.left = w.xs < 0;
     w.right = w.xs + W > a.out_w;
     w.lane_src = w.left ? 0u : static_cast<uint32_t>(w.xs * PB - Wk::MIS);
+    w.own_first = c0 == 0;
+    w.p_right = (a.in_w - 1 >= c0 && a.in_w - 1 < c0 + P) ? a.in_w - 1 - c0 : -1;
+    w.r_a = r_a;
+    w.in_h = a.in_h;
     unsigned char *d = a.dst + static_cast<int64_t>(blockIdx.z) * a.dst_plane_pitch +
                        static_cast<int64_t>(r_a) * a.dst_pitch;
     extern __shared__ __attribute__((aligned(16))) unsigned char xlds[];
@@ -445,96 +538,14 @@ __global__ void __launch_bounds__(256) k_bwd_x2(ResizeArgs a, int32_t ns)
     w.run(ns);
 }
 
-// Border source pixels: add the terms whose row or column tap was clamped onto
-// them (the interior walk above left those out). One thread per border pixel
-// and plane; index k walks row 0, row in_h-1, then columns 0 and in_w-1 of
-// the rows in between. With float16 storage the walk's value is already
-// rounded, so the border pixels are summed here in full (every term) and
-// overwritten: each gradient is rounded once.
-template <int FILTER, typename T, int C>
-__global__ void __launch_bounds__(256) k_bwd_up2_border(ResizeArgs a)
-{
-    constexpr bool kFull = !std::is_same_v<T, float>;
-    using TP = Taps<FILTER>;
-    constexpr int K = TP::K;
-    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t n_rows_part = (a.in_h > 1) ? 2 * a.in_w : a.in_w;
-    const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
-    const int32_t n_cols_part = (a.in_w > 1) ? 2 * inner : inner;
-    if (k >= n_rows_part + n_cols_part)
-        return;
-    int32_t r, c;
-    if (k < n_rows_part) {
-        r = (k < a.in_w) ? 0 : a.in_h - 1;
-        c = k % a.in_w;
-    } else {
-        const int32_t j = k - n_rows_part;
-        r = 1 + j % inner;
-        c = (j < inner) ? 0 : a.in_w - 1;
-    }
-    const int32_t y_lo = first_output<FILTER>(r, a.in_h, a.out_h);
-    const int32_t y_hi = last_output<FILTER>(r, a.in_h, a.out_h);
-    const int32_t x_lo = first_output<FILTER>(c, a.in_w, a.out_w);
-    const int32_t x_hi = last_output<FILTER>(c, a.in_w, a.out_w);
-    const unsigned char *gsrc = a.src + static_cast<int64_t>(blockIdx.y) * a.src_plane_pitch;
-    float extra[C];
-#pragma unroll
-    for (int ch = 0; ch < C; ++ch)
-        extra[ch] = 0.0f;
-    for (int32_t y = y_lo; y <= y_hi; ++y) {
-        int32_t y0;
-        float ty, uy;
-        axis_tap(y, a.in_h, a.out_h, 1, y0, ty, uy);
-        float wy[K];
-        weights<FILTER>(ty, uy, wy);
-        const unsigned char *grow = gsrc + static_cast<int64_t>(y) * a.src_pitch;
-        for (int32_t x = x_lo; x <= x_hi; ++x) {
-            int32_t x0;
-            float tx, ux;
-            axis_tap(x, a.in_w, a.out_w, 1, x0, tx, ux);
-            float wx[K];
-            weights<FILTER>(tx, ux, wx);
-            float w = 0.0f;
-#pragma unroll
-            for (int j = 0; j < K; ++j) {
-                const int32_t ry = y0 + TP::LO + j;
-                if (clampi(ry, 0, a.in_h - 1) != r)
-                    continue;
-#pragma unroll
-                for (int i = 0; i < K; ++i) {
-                    const int32_t cx = x0 + TP::LO + i;
-                    if (clampi(cx, 0, a.in_w - 1) == c && (kFull || ry != r || cx != c))
-                        w += wy[j] * wx[i];
-                }
-            }
-            if (w != 0.0f) {
-                float g[C];
-                Pix<T, C>::load(grow, x, g);
-#pragma unroll
-                for (int ch = 0; ch < C; ++ch)
-                    extra[ch] = __builtin_fmaf(w, g[ch], extra[ch]);
-            }
-        }
-    }
-    unsigned char *orow = a.dst + static_cast<int64_t>(blockIdx.y) * a.dst_plane_pitch +
-                          static_cast<int64_t>(r) * a.dst_pitch;
-    if constexpr (kFull) {
-        Pix<T, C>::store(orow, c, extra);
-    } else {
-        float *out = reinterpret_cast<float *>(orow) + c * C;
-#pragma unroll
-        for (int ch = 0; ch < C; ++ch)
-            out[ch] += extra[ch];
-    }
-}
-
 template <int FILTER, typename T, int C>
 hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
 {
     constexpr int P = (C == 1) ? 4 : 1;
-    // strips of 16 source rows, shortened so that a strip's rows stay well
-    // inside a buffer resource's 2 GiB
-    int32_t ns = 16;
+    // strips of 8 source rows (measured on the 32x3x1024^2 bilinear FP32
+    // adjoint: 8 rows 345 us, 16 rows 360 us, 32 rows 381 us), shortened so
+    // that a strip's rows stay well inside a buffer resource's 2 GiB
+    int32_t ns = 8;
     while (ns > 4 && (2 * ns + 8) * std::max(a.src_pitch, a.dst_pitch) >= (int64_t(1) << 30))
         ns -= 4;
     const int32_t cols_per_block = 256 * P;
@@ -542,10 +553,6 @@ hipError_t launch_bwd_up2(const ResizeArgs &a, hipStream_t stream)
     hipLaunchKernelGGL((k_bwd_x2<FILTER, T, C, P>),
                        dim3((a.in_w + cols_per_block - 1) / cols_per_block, (a.in_h + ns - 1) / ns, a.planes),
                        dim3(256), lds, stream, a, ns);
-    const int32_t inner = a.in_h > 2 ? a.in_h - 2 : 0;
-    const int32_t border = ((a.in_h > 1) ? 2 * a.in_w : a.in_w) + ((a.in_w > 1) ? 2 * inner : inner);
-    hipLaunchKernelGGL((k_bwd_up2_border<FILTER, T, C>), dim3((border + 255) / 256, a.planes), dim3(256), 0,
-                       stream, a);
     return hipGetLastError();
 }
 
