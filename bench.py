@@ -31,6 +31,8 @@ Printed JSON line (one):
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
        [--no-batch] [--no-tune] [--extras]
        python bench.py --paper-sweep   (the paper's tile experiment only)
+       python bench.py --profile WORKLOAD [--steps N] [--tile ...] [--batch-tile ...]
+                       (one workload, eager, fixed shape: what rocprofv3 runs)
 """
 
 from __future__ import annotations
@@ -408,6 +410,30 @@ def cpu_baseline(src_host, target_s: float = 10.0):
             **host_cpu()}
 
 
+def touched_rows(n_in: int, n_out: int, taps: int) -> int:
+    """Source rows (or columns) that some output row reads: the union over
+    output indices y of the clamped taps y0 - lo .. y0 - lo + K - 1 with
+    y0 = floor((2 y + 1) n_in / (2 n_out) - 1/2) (eqs. 1-4). Every row when
+    the tap windows overlap or touch; fewer when shrinking by more than K."""
+    lo = 1 if taps == 4 else 0
+    rows = set()
+    for y in range(n_out):
+        y0 = ((2 * y + 1) * n_in - n_out) // (2 * n_out)
+        for j in range(taps):
+            rows.add(min(max(y0 - lo + j, 0), n_in - 1))
+    return len(rows)
+
+
+def batch_alg_bytes(jobs) -> int:
+    """Algorithmic bytes of a batch: every output pixel written once and every
+    source row that some output row reads (touched_rows) read once."""
+    total = 0
+    for j in jobs:
+        taps = 4 if j.filter == 1 else 2
+        total += touched_rows(j.in_h, j.out_h, taps) * j.in_w * j.channels + j.out_h * j.out_w * j.channels
+    return total
+
+
 def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
     dev = torch.device("cuda:0")
     jobs = fields.batch_jobs(0)
@@ -418,7 +444,7 @@ def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
         d = torch.empty((j.out_h, j.out_w, j.channels), dtype=torch.uint8, device=dev)
         pairs.append((s, d, j.filter))
     out_px = sum(j.out_h * j.out_w for j in jobs)
-    alg = sum(j.in_h * j.in_w * j.channels + j.out_h * j.out_w * j.channels for j in jobs)
+    alg = batch_alg_bytes(jobs)
 
     def per_image():
         for s, d, f in pairs:
@@ -638,6 +664,85 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
     return out
 
 
+def profile_workload(args, torch, xr, fields):
+    """One workload launched eagerly `--steps` times with a fixed launch shape
+    (the library default, or --tile / --batch-tile), nothing captured in a
+    graph and no tuning: the command the rocprofv3 summaries in profiles/ are
+    taken with. Prints one JSON line with the mean launch time from HIP
+    events and the algorithmic bytes per launch."""
+    dev = torch.device("cuda:0")
+    name = args.profile
+    steps = args.steps
+    if name == "copy":  # counter calibration: a plain 1 GiB device copy
+        a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        launch, alg = (lambda i: b.copy_(a)), 2 << 30
+    elif name == "batch":
+        # every job's source is a crop of one 2048 x 2048 field (the same
+        # sizes and work as the benchmark's batch): a few hundred generating
+        # dispatches instead of tens of thousands, which rocprofv3 counter
+        # collection has not survived
+        jobs = fields.batch_jobs(0)
+        base = fields.field_u8_torch(2048, 2048, 4, 7, dev)
+        pairs = []
+        for j in jobs:
+            s = base[:j.in_h, :j.in_w, :j.channels].contiguous()
+            d = torch.empty((j.out_h, j.out_w, j.channels), dtype=torch.uint8, device=dev)
+            pairs.append((s, d, j.filter))
+        tile = xr.tile(*(int(v) for v in args.batch_tile.split(","))) if args.batch_tile else None
+        b = xr.Batch(pairs, tile=tile)
+        launch, alg = (lambda i: b.run()), batch_alg_bytes(jobs)
+    elif name in ("c4_fwd", "c4_adjoint"):
+        x = torch.randn((32, 3, 1024, 1024), device=dev)
+        g = torch.randn((32, 3, 2048, 2048), device=dev)
+        if name == "c4_fwd":
+            y = torch.empty_like(g)
+            launch = lambda i: xr.resize_into(x, y, "bilinear", layout="nchw")
+        else:
+            gx = torch.empty_like(x)
+            launch = lambda i: xr.resize_backward(g, (1024, 1024), "bilinear", out=gx)
+        alg = (x.numel() + g.numel()) * 4
+    elif name == "c5":
+        src = torch.clamp(fields.smooth_field_torch(16384, 16384, 1, 1005, dev)[:, :, 0] / 255.0, 0, 1).half()
+        dst = torch.empty((32768, 32768), dtype=torch.float16, device=dev)
+        launch, alg = (lambda i: xr.resize_into(src, dst, "bicubic")), (src.numel() + dst.numel()) * 2
+    elif name == "c1":
+        src = torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev)
+        dst = torch.empty((1024, 1024), dtype=torch.uint8, device=dev)
+        launch, alg = (lambda i: xr.resize_into(src, dst, "bilinear")), 512 * 512 + 1024 * 1024
+    else:  # C2: x2 / x05, storage u8 / f16 / f32, bicubic RGBA 4096^2
+        direction, _, dname = name.partition("_")
+        n = {"x2": 8192, "x05": 2048}[direction]
+        fld = fields.smooth_field_torch(4096, 4096, 4, 1002, dev)
+        if dname in ("", "u8"):
+            src = torch.clamp(torch.round(fld), 0, 255).to(torch.uint8)
+        else:
+            src = torch.clamp(fld / 255.0, 0.0, 1.0).to({"f16": torch.float16, "f32": torch.float32}[dname])
+        del fld
+        n_buf = max(1, math.ceil(ROTATE_BYTES / (src.numel() * src.element_size() * (1 + (n / 4096) ** 2))))
+        srcs = [src] + [src.clone() for _ in range(n_buf - 1)]
+        dsts = [torch.empty((n, n, 4), dtype=src.dtype, device=dev) for _ in range(n_buf)]
+        if args.tile:
+            xr.set_tile("bicubic", xr._DTYPES[src.dtype], 4, 4096, 4096, n, n,
+                        xr.tile(*(int(v) for v in args.tile.split(","))))
+        launch = lambda i: xr.resize_into(srcs[i % n_buf], dsts[i % n_buf], "bicubic")
+        alg = (4096 * 4096 + n * n) * 4 * src.element_size()
+    for i in range(3):
+        launch(i)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        launch(i)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    print(json.dumps({"profile": name, "launches": steps + 3, "timed_launches": steps,
+                      "mean_ms": round(ms, 5), "alg_bytes": alg,
+                      "gbs": round(alg / ms / 1e6, 1), "hbm_frac": round(alg / ms / 1e6 / HBM_PEAK_GBS, 4)}),
+          flush=True)
+
+
 PAPER_SHAPES = [(8, 8), (32, 4), (32, 16), (4, 8), (8, 4)]
 
 
@@ -698,6 +803,13 @@ def main():
                     help="fixed launch shape KIND,BW,BH,PPX,PPY[,ORDER] (kind 1 gather, 2 strip) instead of tuning")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run a plain 256 MiB device copy (reference for hardware counters)")
+    ap.add_argument("--profile", type=str, default=None,
+                    choices=["x2", "x05", "x2_f16", "x05_f16", "x2_f32", "x05_f32", "c1", "batch", "c4_fwd",
+                             "c4_adjoint", "c5", "copy"],
+                    help="launch one workload eagerly --steps times with a fixed shape (no graph, no "
+                         "tuning; for rocprofv3) and print its mean launch time")
+    ap.add_argument("--batch-tile", type=str, default=None,
+                    help="fixed batched launch shape KIND,BW,BH,PPX,PPY for --profile batch")
     ap.add_argument("--paper-sweep", action="store_true",
                     help="only run the paper's tile-shape experiment (800x800 bilinear x2..x10) and "
                          "print its JSON line")
@@ -717,6 +829,11 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.profile:
+        if "--steps" not in sys.argv:
+            args.steps = 20
+        profile_workload(args, torch, xr, fields)
+        return
     if args.paper_sweep:
         print(json.dumps({"paper_tile_sweep": paper_sweep(torch, xr, fields), "dtype": "u8",
                           "data": "synthetic"}), flush=True)

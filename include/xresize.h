@@ -203,16 +203,20 @@ int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t 
  * section III.B).
  *
  * xr_batch_workspace_bytes(n): bytes of device workspace for n jobs.
- * xr_batch_prepare: validates every job exactly like xr_resize_*, splits
- *   every output into tiles of `tile` (NULL = the shape xr_batch_autotune
- *   chose for this dtype, else 256x1 threads with 14-row strips; two output
- *   columns per thread whatever tile.ppt_x says), orders the jobs
- *   largest-first, and uploads the job table and tile prefix sums to
+ * xr_batch_prepare: validates every job exactly like xr_resize_*, groups
+ *   the jobs by kind (filter x channel count; jobs narrower than the
+ *   filter's taps or than one thread's run form a fifth kind), splits every
+ *   output into tiles of `tile` (NULL = the shape xr_batch_autotune chose for
+ *   this dtype, else 256x1 threads with 14-row strips; block_w a multiple of
+ *   64, block_w * block_h <= 256, ppt_y <= 256; the output columns per
+ *   thread are fixed per kind, tile.ppt_x is ignored), orders each kind's
+ *   jobs largest-first, and uploads the job table and tile prefix sums to
  *   `dev_ws` (device memory, 256-byte aligned, >= xr_batch_workspace_bytes(n))
  *   with an asynchronous copy on `stream`. The host copy of `jobs` may be
  *   reused once the call returns. NOT capturable (XR_ERR_CAPTURE).
  *   All jobs must share one dtype.
- * xr_resize_batched: one launch that processes every tile of every prepared
+ * xr_resize_batched: one persistent launch per job kind present, back to
+ *   back on `stream`, that together process every tile of every prepared
  *   job. Capturable and replayable; it allocates nothing. The workspace must
  *   not be used by two launches at the same time.
  * Each output pixel is bit-identical to the one xr_resize_bilinear /
@@ -233,7 +237,7 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
  * Autotuner of the batched launch (the paper's tile-shape question, sections
  * III.A and IV, asked for a whole batch): prepares `dev_ws` with each
  * candidate shape in turn (NULL = built-in list: 64x4, 128x2 and 256x1
- * threads, strips of 4 to 190 rows; ppt_x is always 2), times `groups` groups
+ * threads, strips of 4 to 190 rows; ppt_x is ignored), times `groups` groups
  * of `reps` launches with HIP events on `stream`, and keeps the shape with
  * the smallest median time per launch. On return `dev_ws` is prepared with
  * that shape, *best / *best_ms (either may be NULL) hold it, and later

@@ -525,7 +525,7 @@ struct BatchInfo {
     int32_t n_jobs;
     int32_t dtype;
     int32_t block_w, block_h;
-    int32_t grid;
+    int32_t grid[xr::kBatchKinds];
 };
 std::mutex g_batch_mu;
 std::map<const void *, BatchInfo> g_batches;
@@ -538,7 +538,7 @@ xr_tile batch_default_tile(int32_t dtype)
     auto it = g_batch_tuned.find(dtype);
     if (it != g_batch_tuned.end())
         return it->second;
-    return xr_tile{XR_KERNEL_STRIP, 256, 1, xr::kBatchPpx, 14, 0};
+    return xr_tile{XR_KERNEL_STRIP, 256, 1, 0, 14, 0};
 }
 
 }  // namespace
@@ -591,9 +591,9 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     } else {
         t = batch_default_tile(dtype);
     }
-    t.ppt_x = xr::kBatchPpx;
+    t.ppt_x = 0;  // fixed per job kind
     if (t.block_w < 64 || t.block_w % 64 != 0 || t.block_h < 1 || t.block_w * t.block_h > 256 ||
-        t.ppt_y < 1 || t.ppt_y > 4096)
+        t.ppt_y < 1 || t.ppt_y > xr::kBatchMaxStrip)
         return fail(XR_ERR_ARG, "batched tile block %dx%d ppt_y %d invalid", t.block_w, t.block_h,
                     t.ppt_y);
     for (int32_t k = 0; k < n_jobs; ++k) {
@@ -620,11 +620,23 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     if (cs != hipStreamCaptureStatusNone)
         return fail(XR_ERR_CAPTURE, "xr_batch_prepare called on a capturing stream");
 
-    // largest output first
+    // grouped by kind, largest output first within a kind
+    const auto fc_of = [&](const xr_job &j) {
+        return (j.filter == XR_BICUBIC ? 2 : 0) + (j.src.channels == 4 ? 1 : 0);
+    };
+    const auto kind_of = [&](const xr_job &j) {
+        const int32_t taps = j.filter == XR_BICUBIC ? 4 : 2;
+        if (j.src.width < taps || j.dst.width < xr::batch_ppx(dtype, j.src.channels))
+            return xr::kBatchNarrow;
+        return fc_of(j);
+    };
     std::vector<int32_t> order(n_jobs);
     for (int32_t k = 0; k < n_jobs; ++k)
         order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+        const int32_t kp = kind_of(jobs[p]), kq = kind_of(jobs[q]);
+        if (kp != kq)
+            return kp < kq;
         const int64_t wp = static_cast<int64_t>(jobs[p].dst.width) * jobs[p].dst.rows * jobs[p].dst.planes;
         const int64_t wq = static_cast<int64_t>(jobs[q].dst.width) * jobs[q].dst.rows * jobs[q].dst.planes;
         return wp > wq;
@@ -632,44 +644,62 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     std::vector<unsigned char> host(xr_batch_workspace_bytes(n_jobs), 0);
     auto *hdr = reinterpret_cast<xr::BatchHeader *>(host.data());
     auto *tab = reinterpret_cast<xr::BatchJob *>(host.data() + xr::kBatchHeaderBytes);
-    const int64_t tile_w = static_cast<int64_t>(t.block_w) * xr::kBatchPpx;
-    int64_t total = 0;
+    for (int32_t k = 0; k < xr::kBatchKinds; ++k)
+        hdr->job_lo[k] = hdr->job_hi[k] = 0;
     for (int32_t k = 0; k < n_jobs; ++k) {
         const xr_job &j = jobs[order[k]];
         xr::BatchJob &b = tab[k];
+        const int32_t kind = kind_of(j);
+        if (k == 0 || tab[k - 1].kind != kind)
+            hdr->job_lo[kind] = k;
+        hdr->job_hi[kind] = k + 1;
         b.a = make_args(j.src, j.dst);
-        b.filter = j.filter;
-        b.channels = j.src.channels;
+        b.kind = kind;
+        b.kind_fc = fc_of(j);
         // a strip walks about ppt_y source rows or ppt_y output rows, whichever
         // is fewer output rows, so shrinking jobs do not make long tiles
-        b.strip_h = static_cast<int32_t>(std::max<int64_t>(
-            1, std::min<int64_t>(t.ppt_y, (static_cast<int64_t>(t.ppt_y) * j.dst.height +
-                                           j.src.height - 1) / j.src.height)));
+        int64_t strip = std::max<int64_t>(
+            1, std::min<int64_t>(t.ppt_y, (static_cast<int64_t>(t.ppt_y) * j.dst.height + j.src.height - 1) /
+                                               j.src.height));
+        // the source rows of a strip, (strip - 1) n_in / n_out + K + 1 at most,
+        // stay below 2^31 bytes (32-bit buffer offsets)
+        const int64_t max_rows = (int64_t(1) << 31) / j.src.row_pitch - 6;
+        strip = std::min<int64_t>(strip, std::max<int64_t>(1, max_rows * j.dst.height / j.src.height));
+        b.strip_h = static_cast<int32_t>(strip);
+        const int64_t tile_w =
+            static_cast<int64_t>(t.block_w) * (kind == xr::kBatchNarrow ? 1 : xr::batch_ppx(dtype, j.src.channels));
         const int64_t tile_h = static_cast<int64_t>(t.block_h) * b.strip_h;
         b.tiles_x = static_cast<int32_t>((j.dst.width + tile_w - 1) / tile_w);
         b.tiles_y = static_cast<int32_t>((j.dst.rows + tile_h - 1) / tile_h);
-        b.tile_begin = total;
-        total += static_cast<int64_t>(b.tiles_x) * b.tiles_y * j.dst.planes;
+        b.tile_begin = hdr->tiles[kind];
+        hdr->tiles[kind] += static_cast<int64_t>(b.tiles_x) * b.tiles_y * j.dst.planes;
     }
-    if (total >= (int64_t(1) << 31))
-        return fail(XR_ERR_ARG, "batch has %lld tiles (limit 2^31)", static_cast<long long>(total));
+    for (int32_t k = 0; k < xr::kBatchKinds; ++k)
+        if (hdr->tiles[k] >= (int64_t(1) << 31))
+            return fail(XR_ERR_ARG, "batch has %lld tiles of one kind (limit 2^31)",
+                        static_cast<long long>(hdr->tiles[k]));
     int dev = 0, cus = 0;
     e = hipGetDevice(&dev);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess)
         return fail_hip(e, "device query");
-    const int32_t per_cu = xr::batched_blocks_per_cu(dtype, t.block_w * t.block_h);
-    const int64_t grid = std::min<int64_t>(static_cast<int64_t>(per_cu) * cus, total);
-    hdr->total_tiles = total;
     hdr->n_jobs = n_jobs;
     hdr->dtype = dtype;
     hdr->block_w = t.block_w;
     hdr->block_h = t.block_h;
     hdr->ppt_y = t.ppt_y;
-    hdr->grid = static_cast<int32_t>(std::max<int64_t>(grid, 1));
-    hdr->ticket = 0;
-    hdr->done = 0;
+    BatchInfo info{n_jobs, dtype, t.block_w, t.block_h, {}};
+    for (int32_t k = 0; k < xr::kBatchKinds; ++k) {
+        if (hdr->tiles[k] == 0)
+            continue;
+        const int32_t per_cu = xr::batched_blocks_per_cu(dtype, k, t.block_w * t.block_h);
+        hdr->grid[k] = static_cast<int32_t>(
+            std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(per_cu) * cus, hdr->tiles[k])));
+        info.grid[k] = hdr->grid[k];
+        hdr->ticket[k] = 0;
+        hdr->done[k] = 0;
+    }
     e = hipMemcpyAsync(dev_ws, host.data(), host.size(), hipMemcpyHostToDevice,
                        static_cast<hipStream_t>(stream));
     if (e == hipSuccess)
@@ -677,7 +707,7 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     if (e != hipSuccess)
         return fail_hip(e, "uploading the job table");
     std::lock_guard<std::mutex> lock(g_batch_mu);
-    g_batches[dev_ws] = BatchInfo{n_jobs, dtype, t.block_w, t.block_h, hdr->grid};
+    g_batches[dev_ws] = info;
     return XR_OK;
 }
 
@@ -722,7 +752,7 @@ int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candida
         const int ppy_list[] = {4, 8, 14, 22, 30, 46, 62, 94, 126, 190};
         for (const auto &b : blocks)
             for (int ppy : ppy_list)
-                cand.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], xr::kBatchPpx, ppy, 0});
+                cand.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], 0, ppy, 0});
     }
     for (size_t k = 0; k < cand.size(); ++k)
         if (cand[k].kernel != XR_KERNEL_STRIP)
@@ -785,10 +815,8 @@ int xr_batch_autotune(const xr_job *jobs, int32_t n_jobs, const xr_tile *candida
         std::lock_guard<std::mutex> lock(g_batch_mu);
         g_batch_tuned[jobs[0].src.dtype] = cand[best_k];
     }
-    if (best) {
+    if (best)
         *best = cand[best_k];
-        best->ppt_x = xr::kBatchPpx;
-    }
     if (best_ms)
         *best_ms = best_t;
     return XR_OK;

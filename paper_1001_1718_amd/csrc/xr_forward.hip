@@ -21,8 +21,9 @@
 //               pixels per row, two source rows per output row, with the
 //               buffer-resource loads and stores of k_x2.
 //  k_strip_lds  any scale, each source row staged once per workgroup in LDS.
-//  k_batched    one persistent launch over the tiles of many jobs, each tile
-//               running the k_strip walk of its job.
+//  k_batch_walk persistent launches over the tiles of many jobs, one per job
+//               kind (filter x channels); one window load per column and
+//               row weights from a per-wavefront LDS table.
 //  k_gather_aa, k_tile_aa  the antialiased filters (support stretched when
 //               shrinking): one pixel per thread from memory, or the block's
 //               source window staged in LDS and filtered separably.
@@ -45,6 +46,22 @@ using namespace dev;
 // ---------------------------------------------------------------------------
 // helpers: contiguous runs of pixels
 // ---------------------------------------------------------------------------
+
+// Storage type code of a pixel type.
+template <typename T>
+struct DType;
+template <>
+struct DType<uint8_t> {
+    static constexpr int32_t kCode = XR_U8;
+};
+template <>
+struct DType<_Float16> {
+    static constexpr int32_t kCode = XR_F16;
+};
+template <>
+struct DType<float> {
+    static constexpr int32_t kCode = XR_F32;
+};
 
 template <typename T, int C>
 struct PixRaw {
@@ -1305,43 +1322,374 @@ __global__ void __launch_bounds__(512) k_x05(ResizeArgs a, int32_t nr, int32_t s
 }
 
 // ---------------------------------------------------------------------------
-// k_batched: one persistent launch over every tile of every job
+// k_batch_walk: persistent launches over the tiles of many jobs
 // ---------------------------------------------------------------------------
 //
-// Workgroups take tiles from a global ticket counter (jobs are ordered largest
-// first, so the long tiles start early and short ones fill the tail). A tile
-// is a (blockDim.x * kBatchPpx) x (blockDim.y * strip_h) block of one plane
-// of one job (strip_h per job: shorter for jobs whose rows shrink); filter and channel count are uniform per tile, so the branch
-// to the right strip body is uniform. The last workgroup to finish resets the
-// counters, so the launch can be replayed (e.g. from a HIP graph) without any
-// host-side clearing.
+// The jobs are grouped by kind (filter x channel count). Each kind has a
+// launch of its own, compiled for it (its own columns per thread and register
+// budget); the launches follow one another on the stream. Within a kind,
+// workgroups take tiles from the kind's ticket counter; its jobs are ordered
+// largest first, so long tiles start early and short ones fill the tail. A
+// tile is (blockDim.x * PPX) columns by (blockDim.y * strip_h) rows of one
+// plane of one job (strip_h per job). The last workgroup of a launch to finish
+// resets its kind's counters, so the launches can be replayed (e.g. from a HIP
+// graph) without host-side clearing. Jobs whose source is narrower than the
+// filter's taps, or whose output is narrower than a run, form a fifth kind
+// that runs the per-tap strip walk.
+//
+// The walk of one thread (SrcWalk) covers PPX adjacent output columns of a
+// strip of output rows:
+//  * columns: a column's K taps are K adjacent source pixels (eqs. 2-5).
+//    Pixels of under 4 bytes are read with one window load of K pixels from
+//    the first tap clamped into the row, the taps then picked out of it with
+//    byte permutes (the identity away from the image edges); wider pixels
+//    with one load per tap at its clamped offset. The last run of a row is
+//    moved left to end at the image edge (its pixels are computed twice, to
+//    the same bits), so every store writes a whole run;
+//  * rows: each source row the strip reads is loaded a few rows ahead and
+//    filtered once into ring slot (row mod K), and every output row is
+//    emitted as soon as its last tap row is filtered, reading its K rows
+//    from slots that are constants of the 4-row unrolled loop; the row taps
+//    advance by a constant quotient and remainder (one division per strip),
+//    and the rows' weights are computed once per strip, one row per lane,
+//    into a table of the wavefront in LDS read back per output row as a
+//    broadcast;
+//  * memory: loads and stores go through buffer resources over the strip's
+//    source rows and output rows.
+// The float32 sequence per output value is the one every kernel uses, so
+// the results are bit-identical to the single-image launches.
 
-template <typename T, int FILTER, int C>
-__device__ __forceinline__ void batched_tile(const ResizeArgs &a, int32_t plane, int32_t col0,
-                                             int32_t r_begin, int32_t r_end)
+// K pixels (TB bytes) of a column's window; 2-byte windows (one-channel uint8
+// bilinear) take one 16-bit load, zero-extended into the window's dword
+template <int TB>
+__device__ __forceinline__ void buf_load_win(unsigned char *dst, __amdgpu_buffer_rsrc_t r, uint32_t off)
 {
-    StripBody<FILTER, T, C, kBatchPpx> body;
-    body.run(a, plane, col0, r_begin, r_end);
+    if constexpr (TB % 4 == 0) {
+        buf_load<TB>(dst, r, off);
+    } else {
+        static_assert(TB == 2, "2-byte windows");
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+        __builtin_memcpy(dst, &v, 4);
+    }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_batched(unsigned char *ws)
+// The column side of the batched walk: PPX adjacent output columns of one
+// thread, their weights and how their taps are loaded from a source row.
+template <int FILTER, typename T, int C, int PPX>
+struct ColTaps {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+    static constexpr int PB = Pix<T, C>::kBytes;
+    static constexpr int TB = K * PB;                 // tap bytes of a column
+    static constexpr int WB = TB < 4 ? 4 : TB;        // their registers
+    static constexpr int OB = PPX * PB;
+    static constexpr bool kWindow = PB <= 2;
+    static constexpr int NS = kWindow ? (TB + 3) / 4 : 1;
+    static constexpr int NO = kWindow ? 1 : K;        // load offsets per column
+    using Win = RawBuf<WB, 4>;
+    using WRow = BatchWeights<K>;
+
+    uint32_t off[PPX][NO];    // byte offsets within a row: the window, or each tap
+    uint32_t psel[PPX][NS];   // window: permute selectors of the taps
+    float wx[PPX][K];
+    __amdgpu_buffer_rsrc_t srsrc;
+    int32_t row_lo, row_hi;   // logical source rows the source resource starts and ends with
+    uint32_t src_pitch;
+
+    // the taps of source row r (clamped into the resource's rows)
+    __device__ __forceinline__ void load_row(Win (&w)[PPX], int32_t r) const
+    {
+        const int32_t rr = clampi(r, row_lo, row_hi);
+        const uint32_t ro = static_cast<uint32_t>(rr - row_lo) * src_pitch;
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            if constexpr (kWindow) {
+                buf_load_win<TB>(w[c].b, srsrc, ro + off[c][0]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < K; ++i)
+                    buf_load<PB>(w[c].b + i * PB, srsrc, ro + off[c][i]);
+            }
+        }
+    }
+
+    // window: tap i of column c is pixel clamp(f + i, 0, n_in - 1) - ld of it
+    __device__ __forceinline__ void pick(Win (&w)[PPX]) const
+    {
+        if constexpr (kWindow) {
+#pragma unroll
+            for (int c = 0; c < PPX; ++c) {
+                uint32_t d[2];
+                __builtin_memcpy(d, w[c].b, 4);
+                d[1] = 0;
+                if constexpr (WB >= 8)
+                    __builtin_memcpy(&d[1], w[c].b + 4, 4);
+                uint32_t r[NS];
+#pragma unroll
+                for (int k = 0; k < NS; ++k)
+                    r[k] = __builtin_amdgcn_perm(d[1], d[0], psel[c][k]);
+                __builtin_memcpy(w[c].b, r, 4 * NS);
+            }
+        }
+    }
+
+    // the load offsets (and selectors) of column c, first tap f; the
+    // window needs n_in >= K
+    __device__ __forceinline__ void make_taps(int c, int32_t f, int32_t in_w)
+    {
+        if constexpr (kWindow) {
+            const int32_t ld = max(0, min(f, in_w - K));
+            off[c][0] = static_cast<uint32_t>(ld * PB);
+            uint32_t sel[NS];
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                sel[k] = 0x0c0c0c0cu;  // bytes past the taps: zero
+#pragma unroll
+            for (int i = 0; i < K; ++i) {
+                const uint32_t idx = static_cast<uint32_t>(clampi(f + i, 0, in_w - 1) - ld);
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    const int pos = i * PB + b;  // byte of the picked taps
+                    const uint32_t from = idx * PB + b;
+                    sel[pos / 4] = (sel[pos / 4] & ~(0xffu << (8 * (pos % 4)))) | (from << (8 * (pos % 4)));
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                psel[c][k] = sel[k];
+        } else {
+#pragma unroll
+            for (int i = 0; i < K; ++i)
+                off[c][i] = static_cast<uint32_t>(clampi(f + i, 0, in_w - 1) * PB);
+        }
+    }
+
+    __device__ __forceinline__ void hfilter(const Win (&w)[PPX], float (&out)[PPX][C]) const
+    {
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            float p[C];
+            decode<T, C>(w[c].b, 0, p);
+            fma_first(out[c], wx[c][0], p);
+#pragma unroll
+            for (int i = 1; i < K; ++i) {
+                decode<T, C>(w[c].b, i, p);
+                fma_next(out[c], wx[c][i], p);
+            }
+        }
+    }
+
+    // columns c0 .. c0 + PPX - 1 (inside the image)
+    __device__ __forceinline__ void set_columns(const ResizeArgs &a, int32_t c0)
+    {
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            int32_t x0;
+            float t, u;
+            source_tap<FILTER>(c0 + c, a.in_w, a.out_w, a.map_off, x0, t, u);
+            weights<FILTER>(t, u, wx[c]);
+            make_taps(c, x0 + TP::LO, a.in_w);
+        }
+    }
+
+    // the source resource over logical rows [lo, hi] clamped into the band
+    __device__ __forceinline__ void set_source(const ResizeArgs &a, int32_t plane, int32_t lo, int32_t hi)
+    {
+        const int32_t band_lo = a.src_row0, band_hi = a.src_row0 + a.src_rows - 1;
+        row_lo = clampi(lo, band_lo, band_hi);
+        row_hi = clampi(hi, band_lo, band_hi);
+        src_pitch = static_cast<uint32_t>(a.src_pitch);
+        const unsigned char *sbase = a.src + static_cast<int64_t>(plane) * a.src_plane_pitch +
+                                     static_cast<int64_t>(row_lo - a.src_row0) * a.src_pitch;
+        srsrc = buf_rsrc(sbase, static_cast<uint32_t>(static_cast<int64_t>(row_hi - row_lo + 1) * a.src_pitch));
+    }
+};
+
+// The row side of the batched walk: the strip's row taps (one floor
+// division for its first and last row, then steps of 2 n_in = sq den + sr)
+// and its row weights, computed one row per lane into the wavefront's LDS
+// table.
+template <int FILTER>
+struct RowTaps {
+    using TP = Taps<FILTER>;
+    static constexpr int K = TP::K;
+    using WRow = BatchWeights<K>;
+    int32_t den, sq, sr;
+    int32_t y_first, rows;
+
+    __device__ __forceinline__ void floor_div(const ResizeArgs &a, int32_t yy, int32_t &qq, int32_t &rr) const
+    {
+        const int32_t num = (2 * yy + a.map_off) * a.in_h - a.map_off * a.out_h;
+        qq = num / den;
+        rr = num - qq * den;
+        if (rr < 0) {
+            qq -= 1;
+            rr += den;
+        }
+    }
+
+    __device__ __forceinline__ void advance(int32_t &q, int32_t &r) const
+    {
+        r += sr;
+        q += sq;
+        if (r >= den) {
+            r -= den;
+            ++q;
+        }
+    }
+
+    __device__ __forceinline__ void init(const ResizeArgs &a, int32_t r_begin, int32_t r_end, WRow *table,
+                                         int32_t tid)
+    {
+        y_first = a.dst_row0 + r_begin;
+        rows = r_end - r_begin;
+        den = 2 * a.out_h;
+        sq = (2 * a.in_h) / den;
+        sr = 2 * a.in_h - sq * den;
+        const int32_t lane = tid & 63;
+        const float rcp_h = __fdiv_rn(1.0f, static_cast<float>(den));
+        for (int32_t base = 0; base < rows; base += 64) {
+            const int32_t yy = y_first + min(base + lane, rows - 1);
+            int32_t y0;
+            float t, u;
+            source_tap_rcp<FILTER>(yy, a.in_h, a.out_h, a.map_off, rcp_h, y0, t, u);
+            WRow e;
+            weights<FILTER>(t, u, e.w);
+            if (base + lane < kBatchMaxStrip)
+                table[base + lane] = e;
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+};
+
+// Cache policy of the batched walk's output stores: non-temporal only. The
+// batch's rows start at arbitrary byte offsets, so a wavefront's run covers
+// partial lines at both ends; measured on the uneven 256-image batch, plain
+// non-temporal stores beat the streaming past-the-L2 policy of the exact
+// walks by 8% (and write-back stores by 12%).
+constexpr int kBatchStore = 2;
+
+// Source-row driven walk (any scale): each source row the strip reads is
+// loaded PD rows ahead, filtered once into ring slot (row mod K), and every
+// output row is emitted as soon as its last tap row is filtered, reading its
+// K rows from slots that are constants of the 4-row unrolled loop.
+template <int FILTER, typename T, int C, int PPX>
+struct SrcWalk : ColTaps<FILTER, T, C, PPX> {
+    using B = ColTaps<FILTER, T, C, PPX>;
+    using typename B::Win;
+    using typename B::WRow;
+    using TP = Taps<FILTER>;
+    static constexpr int K = B::K, PB = B::PB, OB = B::OB, WB = B::WB;
+    static constexpr int PD = PPX * WB <= 32 ? 3 : 1;  // rows loaded ahead
+    static constexpr int Q = PD + 1;                  // divides 4
+
+    float ring[K][PPX][C];
+    Win rawq[Q][PPX];
+    float wy[K];
+    RowTaps<FILTER> rt;
+    const WRow *wt;
+    __amdgpu_buffer_rsrc_t drsrc;
+    uint32_t dst_off, dst_pitch, lane_off;
+    int32_t y, y_end, q, rem, last;
+
+    __device__ __forceinline__ void read_weights()
+    {
+        const WRow e = wt[min(y - rt.y_first, rt.rows - 1)];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            wy[j] = e.w[j];
+    }
+
+    template <int I>
+    __device__ __forceinline__ void emit()
+    {
+        float v[PPX][C];
+#pragma unroll
+        for (int c = 0; c < PPX; ++c) {
+            fma_first(v[c], wy[0], ring[(I + 1) % K][c]);
+#pragma unroll
+            for (int j = 1; j < K; ++j)
+                fma_next(v[c], wy[j], ring[(I + 1 + j) % K][c]);
+        }
+        RawBuf<OB, cmin(16, cgcd(OB, 16))> out;
+        encode_run<T, C, PPX>(v, out);
+        buf_store<OB, kBatchStore>(out.b, drsrc, dst_off + lane_off);
+        ++y;
+        dst_off += dst_pitch;
+        rt.advance(q, rem);
+        last = q + TP::LO + K - 1;
+        read_weights();
+    }
+
+    template <int I>
+    __device__ __forceinline__ void step(int32_t rho, int32_t rho1)
+    {
+        this->load_row(rawq[(I + PD) % Q], min(rho + PD, rho1));
+        if (rho <= rho1) {
+            this->pick(rawq[I % Q]);
+            this->hfilter(rawq[I % Q], ring[I % K]);
+            while (y < y_end && last == rho)
+                emit<I>();
+        }
+    }
+
+    __device__ __forceinline__ void run(const ResizeArgs &a, int32_t plane, int32_t col0, int32_t r_begin,
+                                        int32_t r_end, WRow *table, int32_t tid)
+    {
+        const int32_t c0 = min(col0, a.out_w - PPX);
+        lane_off = col0 < a.out_w ? static_cast<uint32_t>(c0 * PB) : 0x80000000u;
+        this->set_columns(a, c0);
+        rt.init(a, r_begin, r_end, table, tid);
+        wt = table;
+        y = rt.y_first;
+        y_end = y + rt.rows;
+        int32_t q_last, r_last;
+        rt.floor_div(a, y, q, rem);
+        rt.floor_div(a, y_end - 1, q_last, r_last);
+        last = q + TP::LO + K - 1;
+        read_weights();
+        const int32_t rho0 = q + TP::LO;
+        const int32_t rho1 = q_last + TP::LO + K - 1;
+        this->set_source(a, plane, rho0, rho1);
+        unsigned char *dbase = a.dst + static_cast<int64_t>(plane) * a.dst_plane_pitch +
+                               static_cast<int64_t>(r_begin) * a.dst_pitch;
+        drsrc = buf_rsrc(dbase, static_cast<uint32_t>(static_cast<int64_t>(rt.rows) * a.dst_pitch));
+        dst_pitch = static_cast<uint32_t>(a.dst_pitch);
+        dst_off = 0;
+#pragma unroll
+        for (int i = 0; i < PD; ++i)
+            this->load_row(rawq[i % Q], min(rho0 + i, rho1));
+        for (int32_t rho = rho0; rho <= rho1; rho += 4) {
+            step<0>(rho, rho1);
+            step<1>(rho + 1, rho1);
+            step<2>(rho + 2, rho1);
+            step<3>(rho + 3, rho1);
+        }
+    }
+};
+
+template <int FILTER, typename T, int C>
+__global__ void __launch_bounds__(256) k_batch_walk(unsigned char *ws, int32_t kind)
 {
+    constexpr int PPX = batch_ppx(DType<T>::kCode, C);
+    using W = SrcWalk<FILTER, T, C, PPX>;
+    __shared__ typename W::WRow table[4][kBatchMaxStrip];
+    __shared__ uint32_t s_tile;
     BatchHeader *hdr = reinterpret_cast<BatchHeader *>(ws);
     const BatchJob *jobs = reinterpret_cast<const BatchJob *>(ws + kBatchHeaderBytes);
-    const int64_t total = hdr->total_tiles;
-    const int32_t n_jobs = hdr->n_jobs;
-    __shared__ uint32_t s_tile;
-    const bool leader = threadIdx.x == 0 && threadIdx.y == 0;
+    const int64_t total = hdr->tiles[kind];
+    const int32_t j_lo = hdr->job_lo[kind], j_hi = hdr->job_hi[kind];
+    const int32_t tid = static_cast<int32_t>(threadIdx.y * blockDim.x + threadIdx.x);
     for (;;) {
-        if (leader)
-            s_tile = atomicAdd(&hdr->ticket, 1u);
+        if (tid == 0)
+            s_tile = atomicAdd(&hdr->ticket[kind], 1u);
         __syncthreads();
         const int64_t tile = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(s_tile));
         __syncthreads();
         if (tile >= total)
             break;
-        int32_t lo = 0, hi = n_jobs - 1;  // last job whose tile_begin <= tile
+        int32_t lo = j_lo, hi = j_hi - 1;  // last job of the kind whose tile_begin <= tile
         while (lo < hi) {
             const int32_t mid = (lo + hi + 1) >> 1;
             if (jobs[mid].tile_begin <= tile)
@@ -1357,75 +1705,178 @@ __global__ void __launch_bounds__(256) k_batched(unsigned char *ws)
         const int32_t rem = static_cast<int32_t>(local - plane * per_plane);
         const int32_t ty = rem / job.tiles_x;
         const int32_t tx = rem - ty * job.tiles_x;
-        const int32_t col0 = (tx * blockDim.x + threadIdx.x) * kBatchPpx;
+        const int32_t col0 = (tx * static_cast<int32_t>(blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
         const int32_t strip_h = job.strip_h;
         const int32_t r_begin =
-            __builtin_amdgcn_readfirstlane((ty * blockDim.y + threadIdx.y) * strip_h);
+            __builtin_amdgcn_readfirstlane((ty * static_cast<int32_t>(blockDim.y) + threadIdx.y) * strip_h);
+        const int32_t wave_col0 = __builtin_amdgcn_readfirstlane(col0);
+        if (wave_col0 < a.out_w && r_begin < a.dst_rows) {
+            W w;
+            w.run(a, plane, col0, r_begin, min(r_begin + strip_h, a.dst_rows), table[tid >> 6], tid);
+        }
+    }
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(&hdr->done[kind], 1u) == gridDim.x - 1) {
+            atomicExch(&hdr->ticket[kind], 0u);
+            atomicExch(&hdr->done[kind], 0u);
+        }
+    }
+}
+
+// Jobs whose source is narrower than the filter's taps or whose output is
+// narrower than the walk's run (any filter and channel count): the per-tap
+// strip walk, one column per thread.
+template <typename T>
+__global__ void __launch_bounds__(256) k_batch_narrow(unsigned char *ws)
+{
+    constexpr int32_t kind = kBatchNarrow;
+    __shared__ uint32_t s_tile;
+    BatchHeader *hdr = reinterpret_cast<BatchHeader *>(ws);
+    const BatchJob *jobs = reinterpret_cast<const BatchJob *>(ws + kBatchHeaderBytes);
+    const int64_t total = hdr->tiles[kind];
+    const int32_t j_lo = hdr->job_lo[kind], j_hi = hdr->job_hi[kind];
+    const int32_t tid = static_cast<int32_t>(threadIdx.y * blockDim.x + threadIdx.x);
+    for (;;) {
+        if (tid == 0)
+            s_tile = atomicAdd(&hdr->ticket[kind], 1u);
+        __syncthreads();
+        const int64_t tile = static_cast<int64_t>(__builtin_amdgcn_readfirstlane(s_tile));
+        __syncthreads();
+        if (tile >= total)
+            break;
+        int32_t lo = j_lo, hi = j_hi - 1;
+        while (lo < hi) {
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= tile)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const BatchJob &job = jobs[lo];
+        const ResizeArgs a = job.a;
+        const int64_t local = tile - job.tile_begin;
+        const int64_t per_plane = static_cast<int64_t>(job.tiles_x) * job.tiles_y;
+        const int32_t plane = static_cast<int32_t>(local / per_plane);
+        const int32_t rem = static_cast<int32_t>(local - plane * per_plane);
+        const int32_t ty = rem / job.tiles_x;
+        const int32_t tx = rem - ty * job.tiles_x;
+        const int32_t col0 = tx * static_cast<int32_t>(blockDim.x) + static_cast<int32_t>(threadIdx.x);
+        const int32_t r_begin =
+            __builtin_amdgcn_readfirstlane((ty * static_cast<int32_t>(blockDim.y) + threadIdx.y) * job.strip_h);
         if (col0 < a.out_w && r_begin < a.dst_rows) {
-            const int32_t r_end = min(r_begin + strip_h, a.dst_rows);
-            const int32_t kind = job.filter * 2 + (job.channels == 4 ? 1 : 0);
-            switch (kind) {
-            case 0:
-                batched_tile<T, kBilinear, 1>(a, plane, col0, r_begin, r_end);
+            const int32_t r_end = min(r_begin + job.strip_h, a.dst_rows);
+            switch (job.kind_fc) {
+            case 0: {
+                StripBody<kBilinear, T, 1, 1> b;
+                b.run(a, plane, col0, r_begin, r_end);
                 break;
-            case 1:
-                batched_tile<T, kBilinear, 4>(a, plane, col0, r_begin, r_end);
+            }
+            case 1: {
+                StripBody<kBilinear, T, 4, 1> b;
+                b.run(a, plane, col0, r_begin, r_end);
                 break;
-            case 2:
-                batched_tile<T, kBicubic, 1>(a, plane, col0, r_begin, r_end);
+            }
+            case 2: {
+                StripBody<kBicubic, T, 1, 1> b;
+                b.run(a, plane, col0, r_begin, r_end);
                 break;
-            default:
-                batched_tile<T, kBicubic, 4>(a, plane, col0, r_begin, r_end);
+            }
+            default: {
+                StripBody<kBicubic, T, 4, 1> b;
+                b.run(a, plane, col0, r_begin, r_end);
                 break;
+            }
             }
         }
     }
-    if (leader) {
+    if (tid == 0) {
         __threadfence();
-        if (atomicAdd(&hdr->done, 1u) == gridDim.x - 1) {
-            atomicExch(&hdr->ticket, 0u);
-            atomicExch(&hdr->done, 0u);
+        if (atomicAdd(&hdr->done[kind], 1u) == gridDim.x - 1) {
+            atomicExch(&hdr->ticket[kind], 0u);
+            atomicExch(&hdr->done[kind], 0u);
         }
     }
 }
 
-hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h,
-                          int32_t grid, hipStream_t stream)
+namespace {
+// kind = 2 * bicubic + four channels; kBatchNarrow last
+template <typename T, int FILTER, int C>
+void launch_kind(unsigned char *p, dim3 block, const int32_t *grid, hipStream_t stream)
 {
-    unsigned char *p = const_cast<unsigned char *>(static_cast<const unsigned char *>(ws));
-    const dim3 block(block_w, block_h, 1);
-    switch (dtype) {
-    case XR_U8:
-        hipLaunchKernelGGL(k_batched<uint8_t>, dim3(grid), block, 0, stream, p);
-        break;
-    case XR_F16:
-        hipLaunchKernelGGL(k_batched<_Float16>, dim3(grid), block, 0, stream, p);
-        break;
-    default:
-        hipLaunchKernelGGL(k_batched<float>, dim3(grid), block, 0, stream, p);
-        break;
-    }
-    return hipGetLastError();
+    constexpr int kind = (FILTER == kBicubic ? 2 : 0) + (C == 4 ? 1 : 0);
+    if (grid[kind] > 0)
+        hipLaunchKernelGGL((k_batch_walk<FILTER, T, C>), dim3(grid[kind]), block, 0, stream, p, kind);
 }
 
-int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads)
+template <typename T, int FILTER, int C>
+int32_t kind_occupancy(int32_t threads)
 {
     int n = 0;
-    hipError_t e;
-    switch (dtype) {
-    case XR_U8:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<uint8_t>, threads, 0);
-        break;
-    case XR_F16:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<_Float16>, threads, 0);
-        break;
-    default:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batched<float>, threads, 0);
-        break;
-    }
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_walk<FILTER, T, C>, threads, 0);
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
+template <typename T>
+hipError_t launch_batch_kinds(unsigned char *p, int32_t block_w, int32_t block_h, const int32_t *grid,
+                              hipStream_t stream)
+{
+    const dim3 block(block_w, block_h, 1);
+    launch_kind<T, kBilinear, 1>(p, block, grid, stream);
+    launch_kind<T, kBilinear, 4>(p, block, grid, stream);
+    launch_kind<T, kBicubic, 1>(p, block, grid, stream);
+    launch_kind<T, kBicubic, 4>(p, block, grid, stream);
+    if (grid[kBatchNarrow] > 0)
+        hipLaunchKernelGGL(k_batch_narrow<T>, dim3(grid[kBatchNarrow]), block, 0, stream, p);
+    return hipGetLastError();
+}
+
+template <typename T>
+int32_t batch_kind_occupancy(int32_t kind, int32_t threads)
+{
+    switch (kind) {
+    case 0:
+        return kind_occupancy<T, kBilinear, 1>(threads);
+    case 1:
+        return kind_occupancy<T, kBilinear, 4>(threads);
+    case 2:
+        return kind_occupancy<T, kBicubic, 1>(threads);
+    case 3:
+        return kind_occupancy<T, kBicubic, 4>(threads);
+    default: {
+        int n = 0;
+        const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_batch_narrow<T>, threads, 0);
+        return (e == hipSuccess && n > 0) ? n : 1;
+    }
+    }
+}
+}  // namespace
+
+hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h, const int32_t *grid,
+                          hipStream_t stream)
+{
+    unsigned char *p = const_cast<unsigned char *>(static_cast<const unsigned char *>(ws));
+    switch (dtype) {
+    case XR_U8:
+        return launch_batch_kinds<uint8_t>(p, block_w, block_h, grid, stream);
+    case XR_F16:
+        return launch_batch_kinds<_Float16>(p, block_w, block_h, grid, stream);
+    default:
+        return launch_batch_kinds<float>(p, block_w, block_h, grid, stream);
+    }
+}
+
+int32_t batched_blocks_per_cu(int32_t dtype, int32_t kind, int32_t threads)
+{
+    switch (dtype) {
+    case XR_U8:
+        return batch_kind_occupancy<uint8_t>(kind, threads);
+    case XR_F16:
+        return batch_kind_occupancy<_Float16>(kind, threads);
+    default:
+        return batch_kind_occupancy<float>(kind, threads);
+    }
+}
 // ---------------------------------------------------------------------------
 // dispatch
 // ---------------------------------------------------------------------------

@@ -34,38 +34,69 @@ struct ResizeArgs {
 // Entry of the device job table of the batched launch.
 struct BatchJob {
     ResizeArgs a;
-    int32_t filter;
-    int32_t channels;
     int32_t tiles_x;         // tiles per row of the output (per plane)
     int32_t tiles_y;         // tiles per column of the output (per plane)
-    int64_t tile_begin;      // prefix sum of tiles of the jobs before this one
+    int64_t tile_begin;      // tiles of the jobs of the same kind before this one
     int32_t strip_h;         // output rows per thread strip of this job
+    int32_t kind;            // launch of the job (kBatchKinds)
+    int32_t kind_fc;         // 2 * (bicubic) + (four channels)
     int32_t pad_;
 };
 
-// Header of the batched workspace; jobs follow at offset kBatchHeaderBytes.
+// Launches of the batched resize, one per job kind: kinds 0-3 are
+// 2 * (bicubic) + (four channels); kind 4 holds the jobs with a source
+// narrower than the filter's taps or an output narrower than the walk's run.
+constexpr int32_t kBatchKinds = 5;
+constexpr int32_t kBatchNarrow = 4;
+
+// Header of the batched workspace; jobs follow at offset kBatchHeaderBytes,
+// grouped by kind.
 struct BatchHeader {
-    int64_t total_tiles;
     int32_t n_jobs;
     int32_t dtype;
     int32_t block_w;         // threads per workgroup along x
     int32_t block_h;         // thread rows per workgroup
     int32_t ppt_y;           // rows per thread strip (before per-job scaling)
-    int32_t grid;            // workgroups of the persistent launch
-    uint32_t ticket;         // next tile to hand out (self-resetting)
-    uint32_t done;           // workgroups that have finished (self-resetting)
+    int32_t pad_;
+    int32_t job_lo[kBatchKinds];    // jobs [job_lo, job_hi) are of kind k
+    int32_t job_hi[kBatchKinds];
+    int64_t tiles[kBatchKinds];     // tiles of kind k
+    int32_t grid[kBatchKinds];      // workgroups of kind k's launch (0: no launch)
+    uint32_t ticket[kBatchKinds];   // next tile to hand out (self-resetting)
+    uint32_t done[kBatchKinds];     // workgroups that have finished (self-resetting)
 };
 constexpr size_t kBatchHeaderBytes = 256;
+static_assert(sizeof(BatchHeader) <= kBatchHeaderBytes, "batch header");
+
+// Longest thread strip of the batched walk (rows of its per-wavefront weight
+// table in LDS).
+constexpr int32_t kBatchMaxStrip = 256;
+
+// Row weights of one output row in that table.
+template <int K>
+struct alignas(K * 4) BatchWeights {
+    float w[K];
+};
+
+// Output columns per thread of the batched walk, per storage type and channel
+// count: runs of 8 to 16 bytes per thread (the narrow kind: one column).
+constexpr int32_t batch_ppx(int32_t dtype, int32_t channels)
+{
+    return dtype == XR_U8 ? (channels == 1 ? 8 : 2)
+         : dtype == XR_F16 ? (channels == 1 ? 8 : 2)
+                           : (channels == 1 ? 4 : 1);
+}
 
 // Shape of an axis that a kernel can specialise on.
 enum AxisMode : int32_t { kGeneral = 0, kUp2 = 1, kDown2 = 2 };
 
 hipError_t launch_forward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
                           const xr_tile &tile, int32_t mode, hipStream_t stream);
-hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h,
-                          int32_t grid, hipStream_t stream);
-// Workgroups of the batched kernel that fit on one compute unit.
-int32_t batched_blocks_per_cu(int32_t dtype, int32_t threads);
+// The batched launches of a prepared workspace: one per kind with grid[kind] > 0.
+hipError_t launch_batched(const void *ws, int32_t dtype, int32_t block_w, int32_t block_h, const int32_t *grid,
+                          hipStream_t stream);
+// Workgroups of the batched walk of `kind` that fit on one compute unit.
+int32_t batched_blocks_per_cu(int32_t dtype, int32_t kind, int32_t threads);
 hipError_t launch_backward(const ResizeArgs &a, int32_t filter, int32_t dtype, int32_t channels,
                            hipStream_t stream);
 // False when the adjoint's smallest LDS tile cannot hold the output rows of
@@ -130,10 +161,5 @@ constexpr size_t kLdsBudget = 64 * 1024;
 // ResizeArgs; pixels of fewer than 4 bytes are staged as 4-byte words).
 bool strip_lds_fits(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t out_w,
                     int32_t block_w, bool aligned4);
-// Output columns per thread of the batched kernel (both channel counts). The
-// kernel holds every job kind's walk, so its registers are the largest
-// walk's: two columns keep it at 4 waves per SIMD (four columns needed 166
-// VGPRs, 3 waves, and ran 14% slower on the uneven batch).
-constexpr int32_t kBatchPpx = 2;
 
 }  // namespace xr

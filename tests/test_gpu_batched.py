@@ -7,6 +7,8 @@
   eager result every time (the ticket counter resets itself);
 * the full 256-job batch: bitwise equal to 256 per-image launches;
 * FP16 interleaved and FP32 planar (NCHW, several planes per job) batches;
+* narrow, short and strongly scaled jobs of every kind and storage type
+  (taps clamped on both sides of a column, strips of 1 to 256 rows);
 * the batch autotuner keeps results bitwise unchanged;
 * host-side validation of prepare (capture, workspace, dtype mix).
 """
@@ -153,13 +155,53 @@ def test_float_batches(dtype):
             compare(got, planes, j.out_h, j.out_w, f, rows=rows, what=f"f32 job {k}")
 
 
+# (in_h, in_w, out_h, out_w): images narrower or shorter than the taps,
+# shrinks of 4x and more (row and column windows that do not overlap),
+# enlargements of 4x and more, ragged sizes
+EDGE_SHAPES = [(1, 1, 5, 7), (2, 3, 9, 4), (3, 2, 1, 1), (5, 3, 17, 2), (7, 1, 3, 40), (64, 5, 16, 300),
+               (300, 9, 75, 2), (13, 600, 200, 37), (40, 40, 160, 160), (200, 800, 40, 150),
+               (33, 130, 131, 519)]
+EDGE_TILES = [None, (64, 4, 1), (256, 1, 256), (128, 2, 64)]
+
+
+@pytest.mark.parametrize("dtype", [torch.uint8, torch.float16, torch.float32], ids=["u8", "f16", "f32"])
+def test_batch_narrow_and_extreme_jobs(dtype):
+    rng = np.random.default_rng(31)
+    pairs, specs = [], []
+    for k, (ih, iw, oh, ow) in enumerate(EDGE_SHAPES):
+        for ch in (1, 4):
+            for f in (0, 1):
+                if dtype == torch.uint8:
+                    s = torch.from_numpy(rng.integers(0, 256, (ih, iw, ch), dtype=np.uint8)).to(DEV)
+                else:
+                    s = torch.from_numpy(rng.random((ih, iw, ch)).astype(np.float32)).to(dtype).to(DEV)
+                d = torch.empty((oh, ow, ch), dtype=dtype, device=DEV)
+                pairs.append((s, d, f))
+                specs.append((ih, iw, oh, ow, ch, f))
+    ref = _per_image(pairs)
+    for t in EDGE_TILES:
+        tile = None if t is None else xr.tile(xr.XR_KERNEL_STRIP, t[0], t[1], 0, t[2])
+        b = xr.Batch(pairs, tile=tile)
+        for _, d, _ in pairs:
+            d.fill_(3)
+        b.run()
+        torch.cuda.synchronize()
+        for k, ((_, d, _), r) in enumerate(zip(pairs, ref)):
+            assert torch.equal(d, r), f"tile {t}: job {k} {specs[k]} differs from the per-image launch"
+    for k, ((s, d, f), sp) in enumerate(zip(pairs, specs)):
+        ih, iw, oh, ow, ch, _ = sp
+        rows = np.unique(np.array([0, oh // 2, oh - 1]))
+        got = d[torch.from_numpy(rows).to(DEV)].cpu().numpy()[None]
+        compare(got, s.cpu().numpy(), oh, ow, f, rows=rows, what=f"job {k} {sp}")
+
+
 def test_batch_autotune_picks_a_candidate_and_keeps_results():
     jobs, pairs = _make_batch(seed=3, count=24, side_hi=512, content="field")
     ref = _per_image(pairs)
     b = xr.Batch(pairs)
-    # the batched kernel takes two output columns per thread (ppt_x 2)
-    cands = [xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 2, 8), xr.tile(xr.XR_KERNEL_STRIP, 256, 1, 2, 14),
-             xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 2, 30)]
+    # the columns per thread are fixed per job kind (ppt_x is ignored)
+    cands = [xr.tile(xr.XR_KERNEL_STRIP, 64, 4, 0, 8), xr.tile(xr.XR_KERNEL_STRIP, 256, 1, 0, 14),
+             xr.tile(xr.XR_KERNEL_STRIP, 128, 2, 0, 30)]
     best, ms = b.autotune(candidates=cands, reps=2, groups=3)
     assert ms > 0 and best.as_tuple() in [c.as_tuple() for c in cands]
     for _, d, _ in pairs:
@@ -169,7 +211,7 @@ def test_batch_autotune_picks_a_candidate_and_keeps_results():
     assert all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
     # the built-in candidate list, then a batch prepared with the tuned default
     best, ms = b.autotune(reps=1, groups=1)
-    assert ms > 0 and best.kernel == xr.XR_KERNEL_STRIP and best.ppt_x == 2
+    assert ms > 0 and best.kernel == xr.XR_KERNEL_STRIP and best.ppt_x == 0
     b2 = xr.Batch(pairs)
     for _, d, _ in pairs:
         d.zero_()
