@@ -234,6 +234,22 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
 int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): xr_batch_prepare + xr_resize_batched in
+ * one call whose workspace is a static array of the library in device memory
+ * instead of a caller's buffer. It validates exactly like xr_batch_prepare
+ * (same error codes), uploads the job table with a copy on `stream` that it
+ * waits for, and launches like xr_resize_batched; outputs are bit-identical
+ * to that pair's. At most 1024 jobs per call (XR_ERR_WORKSPACE beyond).
+ * Allocates nothing: no hipMalloc, hipFree or allocating library call. Each
+ * GPU holds one such workspace (128.25 KiB) until the process ends, shared
+ * by every call on that GPU: calls whose launches can overlap on one GPU (on
+ * different streams) race, and must be ordered by the caller (one stream, or
+ * a synchronisation between them). NOT capturable (XR_ERR_CAPTURE).
+ */
+int xr_resize_batched_static(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *stream);
+
+/*
  * Autotuner of the batched launch (the paper's tile-shape question, sections
  * III.A and IV, asked for a whole batch): prepares `dev_ws` with each
  * candidate shape in turn (NULL = built-in list: 64x4, 128x2 and 256x1

@@ -1,7 +1,7 @@
 // C-ABI layer of libxresize.so: argument validation (always before any HIP
 // call), launch-shape selection, the batched job table, tuning, and error
 // reporting. The kernels live in xr_forward.hip and xr_backward.hip.
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdarg>
@@ -541,47 +541,48 @@ xr_tile batch_default_tile(int32_t dtype)
     return xr_tile{XR_KERNEL_STRIP, 256, 1, 0, 14, 0};
 }
 
-}  // namespace
+// ---- the batched launch without allocation ------------------------------
+//
+// xr_resize_batched_static keeps its workspace in `scratch`, a file-scope
+// device array that every GPU the library runs on holds until the process
+// ends. Host code never uses the array's name as an address: each device's
+// address is looked up once (hipGetSymbolAddress, with that device current)
+// and kept in g_scratch_ptr.
+constexpr int32_t kStaticMaxJobs = 1024;
+constexpr size_t kScratchBytes = xr::kBatchHeaderBytes + kStaticMaxJobs * sizeof(xr::BatchJob);
+constexpr int kMaxDevices = 64;
 
-extern "C" {
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
-int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+std::mutex g_static_mu;                  // the staging buffers below and g_scratch_ptr
+void *g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch` per device
+unsigned char g_static_stage[kScratchBytes];
+int32_t g_static_order[kStaticMaxJobs];
+
+// this device's address of `scratch` (looked up on its first use)
+int scratch_address(int dev, void **out)
 {
-    return resize_common(src, dst, tile, XR_BILINEAR, XR_MAP_HALF_PIXEL, stream);
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(XR_ERR_ARG, "device %d beyond the %d the static workspace supports", dev, kMaxDevices);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return fail_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!p)
+            return fail(XR_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return XR_OK;
 }
 
-int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+// Validates a batch and builds its workspace image (header and job table,
+// xr_batch_workspace_bytes(n_jobs) bytes) in host memory `host`; `order`
+// holds n_jobs indices of scratch. No device memory is touched.
+int build_batch(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, unsigned char *host, int32_t *order,
+                BatchInfo &info, void *stream, const char *caller)
 {
-    return resize_common(src, dst, tile, XR_BICUBIC, XR_MAP_HALF_PIXEL, stream);
-}
-
-int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t mapping,
-              const xr_tile *tile, void *stream)
-{
-    return resize_common(src, dst, tile, filter, mapping, stream);
-}
-
-size_t xr_batch_workspace_bytes(int32_t n_jobs)
-{
-    if (n_jobs < 1)
-        return 0;
-    return xr::kBatchHeaderBytes + static_cast<size_t>(n_jobs) * sizeof(xr::BatchJob);
-}
-
-int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *dev_ws,
-                     size_t ws_bytes, void *stream)
-{
-    if (!jobs)
-        return fail(XR_ERR_NULL, "jobs is NULL");
-    if (n_jobs < 1)
-        return fail(XR_ERR_ARG, "n_jobs = %d (must be >= 1)", n_jobs);
-    if (!dev_ws)
-        return fail(XR_ERR_WORKSPACE, "workspace is NULL");
-    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
-        return fail(XR_ERR_WORKSPACE, "workspace is not 256-byte aligned");
-    if (ws_bytes < xr_batch_workspace_bytes(n_jobs))
-        return fail(XR_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
-                    xr_batch_workspace_bytes(n_jobs));
     const int32_t dtype = jobs[0].src.dtype;
     xr_tile t{};
     if (tile && tile->kernel != XR_KERNEL_AUTO) {
@@ -618,7 +619,7 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     if (e != hipSuccess)
         return fail_hip(e, "hipStreamIsCapturing");
     if (cs != hipStreamCaptureStatusNone)
-        return fail(XR_ERR_CAPTURE, "xr_batch_prepare called on a capturing stream");
+        return fail(XR_ERR_CAPTURE, "%s called on a capturing stream", caller);
 
     // grouped by kind, largest output first within a kind
     const auto fc_of = [&](const xr_job &j) {
@@ -630,20 +631,21 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
             return xr::kBatchNarrow;
         return fc_of(j);
     };
-    std::vector<int32_t> order(n_jobs);
+    // (std::sort with the job index as the last key: the same order as a
+    // stable sort, and no temporary buffer)
     for (int32_t k = 0; k < n_jobs; ++k)
         order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int32_t p, int32_t q) {
+    std::sort(order, order + n_jobs, [&](int32_t p, int32_t q) {
         const int32_t kp = kind_of(jobs[p]), kq = kind_of(jobs[q]);
         if (kp != kq)
             return kp < kq;
         const int64_t wp = static_cast<int64_t>(jobs[p].dst.width) * jobs[p].dst.rows * jobs[p].dst.planes;
         const int64_t wq = static_cast<int64_t>(jobs[q].dst.width) * jobs[q].dst.rows * jobs[q].dst.planes;
-        return wp > wq;
+        return wp != wq ? wp > wq : p < q;
     });
-    std::vector<unsigned char> host(xr_batch_workspace_bytes(n_jobs), 0);
-    auto *hdr = reinterpret_cast<xr::BatchHeader *>(host.data());
-    auto *tab = reinterpret_cast<xr::BatchJob *>(host.data() + xr::kBatchHeaderBytes);
+    std::memset(host, 0, xr_batch_workspace_bytes(n_jobs));
+    auto *hdr = reinterpret_cast<xr::BatchHeader *>(host);
+    auto *tab = reinterpret_cast<xr::BatchJob *>(host + xr::kBatchHeaderBytes);
     for (int32_t k = 0; k < xr::kBatchKinds; ++k)
         hdr->job_lo[k] = hdr->job_hi[k] = 0;
     for (int32_t k = 0; k < n_jobs; ++k) {
@@ -689,7 +691,7 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
     hdr->block_w = t.block_w;
     hdr->block_h = t.block_h;
     hdr->ppt_y = t.ppt_y;
-    BatchInfo info{n_jobs, dtype, t.block_w, t.block_h, {}};
+    info = BatchInfo{n_jobs, dtype, t.block_w, t.block_h, {}};
     for (int32_t k = 0; k < xr::kBatchKinds; ++k) {
         if (hdr->tiles[k] == 0)
             continue;
@@ -700,8 +702,58 @@ int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, vo
         hdr->ticket[k] = 0;
         hdr->done[k] = 0;
     }
-    e = hipMemcpyAsync(dev_ws, host.data(), host.size(), hipMemcpyHostToDevice,
-                       static_cast<hipStream_t>(stream));
+    return XR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int xr_resize_bilinear(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, XR_BILINEAR, XR_MAP_HALF_PIXEL, stream);
+}
+
+int xr_resize_bicubic(const xr_image *src, const xr_image *dst, const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, XR_BICUBIC, XR_MAP_HALF_PIXEL, stream);
+}
+
+int xr_resize(const xr_image *src, const xr_image *dst, int32_t filter, int32_t mapping,
+              const xr_tile *tile, void *stream)
+{
+    return resize_common(src, dst, tile, filter, mapping, stream);
+}
+
+size_t xr_batch_workspace_bytes(int32_t n_jobs)
+{
+    if (n_jobs < 1)
+        return 0;
+    return xr::kBatchHeaderBytes + static_cast<size_t>(n_jobs) * sizeof(xr::BatchJob);
+}
+
+int xr_batch_prepare(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *dev_ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (!jobs)
+        return fail(XR_ERR_NULL, "jobs is NULL");
+    if (n_jobs < 1)
+        return fail(XR_ERR_ARG, "n_jobs = %d (must be >= 1)", n_jobs);
+    if (!dev_ws)
+        return fail(XR_ERR_WORKSPACE, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_ws) % 256 != 0)
+        return fail(XR_ERR_WORKSPACE, "workspace is not 256-byte aligned");
+    if (ws_bytes < xr_batch_workspace_bytes(n_jobs))
+        return fail(XR_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                    xr_batch_workspace_bytes(n_jobs));
+    std::vector<unsigned char> host(xr_batch_workspace_bytes(n_jobs));
+    std::vector<int32_t> order(n_jobs);
+    BatchInfo info{};
+    const int rc = build_batch(jobs, n_jobs, tile, host.data(), order.data(), info, stream, "xr_batch_prepare");
+    if (rc)
+        return rc;
+    hipError_t e = hipMemcpyAsync(dev_ws, host.data(), host.size(), hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
     if (e == hipSuccess)
         e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
@@ -727,6 +779,43 @@ int xr_resize_batched(const void *dev_ws, int32_t n_jobs, void *stream)
         return fail(XR_ERR_ARG, "n_jobs = %d but the workspace holds %d jobs", n_jobs, info.n_jobs);
     const hipError_t e = xr::launch_batched(dev_ws, info.dtype, info.block_w, info.block_h, info.grid,
                                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "batched launch");
+    return XR_OK;
+}
+
+int xr_resize_batched_static(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, void *stream)
+{
+    if (!jobs)
+        return fail(XR_ERR_NULL, "jobs is NULL");
+    if (n_jobs < 1)
+        return fail(XR_ERR_ARG, "n_jobs = %d (must be >= 1)", n_jobs);
+    if (n_jobs > kStaticMaxJobs)
+        return fail(XR_ERR_WORKSPACE, "n_jobs = %d exceeds the static workspace (%d jobs)", n_jobs,
+                    kStaticMaxJobs);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    BatchInfo info{};
+    int rc = build_batch(jobs, n_jobs, tile, g_static_stage, g_static_order, info, stream,
+                         "xr_resize_batched_static");
+    if (rc)
+        return rc;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipGetDevice");
+    void *ws = nullptr;
+    rc = scratch_address(dev, &ws);
+    if (rc)
+        return rc;
+    // the upload writes the whole header, so the tickets start at zero; the
+    // staging buffer is reused by the next call, hence the synchronisation
+    e = hipMemcpyAsync(ws, g_static_stage, xr_batch_workspace_bytes(n_jobs), hipMemcpyHostToDevice,
+                       static_cast<hipStream_t>(stream));
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return fail_hip(e, "uploading the job table");
+    e = xr::launch_batched(ws, info.dtype, info.block_w, info.block_h, info.grid, static_cast<hipStream_t>(stream));
     if (e != hipSuccess)
         return fail_hip(e, "batched launch");
     return XR_OK;
