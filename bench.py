@@ -26,10 +26,16 @@ Printed JSON line (one):
               images/s, outputs bitwise identical across the three
   hbm_reference  plain torch fill and copy of 256 MiB: the bandwidth this
               GPU reaches with no arithmetic
-  extras      (with --extras) other storage types and workloads
+  configs     the other configurations: C1 (bilinear x2 of a 512^2 uint8
+              image), C2 (bicubic x2 and x0.5 of the 4096^2 RGBA image in
+              uint8, float16 and float32), C4 (bilinear x2 of a float32 NCHW
+              32x3x1024^2 tensor, forward and adjoint), C5 (bicubic x2 of a
+              16384^2 float16 image, whole and in 16 row bands): algorithmic
+              bytes, kernel time, fraction of the HBM peak, the oracle's rate;
+              with --extras also the other filters and maps
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-       [--no-batch] [--no-tune] [--extras]
+       [--no-batch] [--no-tune] [--no-configs] [--extras]
        python bench.py --paper-sweep   (the paper's tile experiment only)
        python bench.py --profile WORKLOAD [--steps N] [--tile ...] [--batch-tile ...]
                        (one workload, eager, fixed shape: what rocprofv3 runs)
@@ -52,7 +58,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 78.6  # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops x 2.4 GHz
 ROTATE_BYTES = 1 << 30
-KERNEL_SOURCES = ["xr_forward.hip", "xr_device.hpp", "xr_internal.h"]
+KERNEL_SOURCES = ["xr_forward.hip", "xr_backward.hip", "xr_device.hpp", "xr_buffer.hpp", "xr_internal.h"]
+HEADLINE_PROFILE = "c2_bicubic_x2_u8_rgba.md"
 
 
 def log(msg: str) -> None:
@@ -69,8 +76,10 @@ def kernel_hash() -> str:
 
 def read_valu(name: str, tile, kernel_s: float):
     """VALU issue time per launch from a committed instruction-counter summary
-    (SQ_INSTS_VALU x cycles per instruction / SIMDs / clock), when it was taken
-    on these kernel sources and this launch shape; else None."""
+    (SQ_INSTS_VALU x cycles per instruction / SIMDs / clock, between the
+    two-cycle rate of VOP2 multiply-adds and the four-cycle rate of the
+    conversions), when it was taken on these kernel sources; else None. The
+    summary's launch shape is reported with it."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -83,14 +92,15 @@ def read_valu(name: str, tile, kernel_s: float):
     try:
         if vals.get("kernel_sources_sha256_16") != kernel_hash():
             return None
-        want = [int(x) for x in vals["tile"].split(",")]
-        have = [tile.kernel, tile.block_w, tile.block_h, tile.ppt_x, tile.ppt_y, tile.order]
-        if want != have:
-            return None
+        # the counters were taken with the summary's launch shape; the
+        # instruction count of another strip height differs by its prologue
         insts = int(vals["SQ_INSTS_VALU"])
-        issue_s = insts * int(vals["cycles_per_valu_inst"]) / int(vals["simds"]) / (float(vals["clock_ghz"]) * 1e9)
-        return {"valu_insts_per_launch": insts, "issue_us": round(issue_s * 1e6, 1),
-                "issue_frac": round(issue_s / kernel_s, 3)}
+        per_cycle = int(vals["simds"]) * float(vals["clock_ghz"]) * 1e9
+        slow = insts * int(vals["cycles_per_valu_inst"]) / per_cycle
+        fast = insts * int(vals["cycles_per_valu_inst_fast"]) / per_cycle
+        return {"valu_insts_per_launch": insts, "profile_tile": vals["tile"],
+                "issue_us_range": [round(fast * 1e6, 1), round(slow * 1e6, 1)],
+                "issue_frac_range": [round(fast / kernel_s, 3), round(slow / kernel_s, 3)]}
     except (KeyError, ValueError, ZeroDivisionError):
         return None
 
@@ -116,6 +126,17 @@ def read_pmc(name: str):
         return fetch * f_fetch + write * f_write
     except (KeyError, ValueError, ZeroDivisionError):
         return None
+
+
+def profile_fields(name, alg):
+    """The profiles/ summary of a configuration's kernel: its name and, when it
+    was taken on these kernel sources, the HBM bytes per launch it measured
+    (traffic) and their ratio to the algorithmic bytes."""
+    if not name or not os.path.exists(os.path.join(ROOT, "profiles", name)):
+        return {}
+    traffic = read_pmc(name)
+    return {"profile": name, "traffic": None if traffic is None else int(traffic),
+            "traffic_over_alg": None if traffic is None else round(traffic / alg, 3)}
 
 
 def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
@@ -240,14 +261,15 @@ def headline(args, torch, xr, fields):
     kernel_s = stats["mean_ms"] / 1e3
     alg = in_bytes + out_bytes
     achieved = alg / kernel_s / 1e9
-    traffic = read_pmc("pmc_resize_bicubic_x2_u8rgba.txt")
+    traffic = read_pmc(HEADLINE_PROFILE)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
                 "alg_bytes_per_launch": alg, "kernel_ms": {k: round(v, 5) for k, v in stats.items()},
                 "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2),
                 # the FP32 VALU check: instruction issue time from the counters
-                "valu": read_valu("sq_k_strip_up2_bicubic_x2_u8rgba.txt", resolved, kernel_s),
+                "valu": read_valu(HEADLINE_PROFILE, resolved, kernel_s),
+                "profile": HEADLINE_PROFILE,
                 # and the algorithmic arithmetic rate: separable Keys x2 takes 24
                 # FP32 multiply-adds per output pixel (4 taps x 4 channels
                 # vertically, half that horizontally per output row), against
@@ -526,15 +548,26 @@ def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
         "output_gpixel": round(out_px / 1e9, 3),
         "persistent_ms": round(launch_ms, 4),
         "persistent_gbs": round(alg / (launch_ms / 1e3) / 1e9, 1),
+        "alg_bytes": alg,
+        "hbm_frac": round(alg / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+        **profile_fields("c3_batch_256_uneven_u8.md", alg),
     }
 
 
-def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True):
-    """Gpixel/s and GB/s of the other storage types and workloads, each with
-    the oracle's rate on a sample of the same workload (about 1 s of host time;
-    `cpu_mpx_s`, the cores it used and its sample) unless cpu is False."""
+def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True, breadth: bool = False):
+    """Every configuration of the workload table besides the headline and the
+    batch (C1, C2 in three storage types and both directions, C4 forward and
+    adjoint, C5 whole and in row bands): per launch the algorithmic bytes,
+    the mean kernel time from HIP events, GB/s and the fraction of the HBM
+    peak, the tuned launch shape, and the oracle's rate on a sample of the
+    same workload (about 1 s of host time; `cpu_mpx_s`, the cores it used and
+    its sample) unless cpu is False. `profile` names the rocprofv3 summary in
+    profiles/ of the configuration's kernel. With breadth, also the other
+    filters and maps and two more adjoints."""
     dev = torch.device("cuda:0")
-    out = {}
+    out = {"C1": {}, "C2": {}, "C4": {}, "C5": {}}
+    if breadth:
+        out["breadth"] = {}
 
     def oracle_rate(src, out_hw, mode, layout, mapping="half_pixel"):
         if not cpu:
@@ -549,8 +582,8 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         return {"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
                 "cpu_sample": f"{n_rows} rows x {passes} passes" if passes > 1 else f"{n_rows} rows"}
 
-    def measure(name, make_src, out_shape, mode, layout="hwc", out_dtype=None, mapping="half_pixel",
-                rotate=True, all_kinds=False):
+    def measure(group, name, make_src, out_shape, mode, layout="hwc", mapping="half_pixel", rotate=True,
+                all_kinds=False, profile=None):
         src0 = make_src()
         in_bytes = src0.numel() * src0.element_size()
         out_bytes = math.prod(out_shape) * src0.element_size()
@@ -579,38 +612,48 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         g_us = graph_launch_us(launch, n_buf, torch)
         # pixels: H * W for interleaved images, N * C * H * W for planar tensors
         px = math.prod(out_shape[:2]) if layout == "hwc" else math.prod(out_shape)
-        out[name] = {"kernel_us": round(k_s * 1e6, 2), "gpixel_s": round(px / k_s / 1e9, 2), "tile": repr(tile),
-                     "buffers": n_buf, "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2),
-                     "graph_us": round(g_us, 2),
-                     "gbs": round((in_bytes + out_bytes) / k_s / 1e9, 1),
-                     "hbm_frac": round((in_bytes + out_bytes) / k_s / 1e9 / HBM_PEAK_GBS, 4),
-                     **oracle_rate(src0, out_hw, mode, layout, mapping)}
-        log(f"extra {name}: {out[name]}")
+        alg = in_bytes + out_bytes
+        out[group][name] = {
+            "alg_bytes": alg, "kernel_us": round(k_s * 1e6, 2), "gbs": round(alg / k_s / 1e9, 1),
+            "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4), "gpixel_s": round(px / k_s / 1e9, 2),
+            "tile": repr(tile), "buffers": n_buf,
+            "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2), "graph_us": round(g_us, 2),
+            **profile_fields(profile, alg),
+            **oracle_rate(src0, out_hw, mode, layout, mapping)}
+        log(f"{group} {name}: {out[group][name]}")
         del srcs, dsts
         torch.cuda.empty_cache()
 
+    measure("C1", "bilinear_x2_u8_512_rotating",
+            lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev), (1024, 1024), "bilinear",
+            all_kinds=True, profile="c1_bilinear_x2_u8_512.md")
+    measure("C1", "bilinear_x2_u8_512_same_buffers",
+            lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev), (1024, 1024), "bilinear",
+            rotate=False, all_kinds=True)
     fld = fields.smooth_field_torch(4096, 4096, 4, 1002, dev)
     unit = torch.clamp(fld / 255.0, 0.0, 1.0)
     u8 = torch.clamp(torch.round(fld), 0, 255).to(torch.uint8)
+    del fld
     for dname, t in [("u8", u8), ("f16", unit.half()), ("f32", unit.float())]:
-        for direction, n in [("x2", 8192), ("x0.5", 2048)]:
-            measure(f"c2_bicubic_{direction}_{dname}_rgba", lambda t=t: t, (n, n, 4), "bicubic")
-    measure("nearest_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "nearest")
-    measure("bicubic_aa_x0.5_u8_rgba", lambda: u8, (2048, 2048, 4), "bicubic_aa")
-    measure("bilinear_aa_x0.25_u8_rgba", lambda: u8, (1024, 1024, 4), "bilinear_aa")
-    measure("bilinear_paper_map_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "bilinear", mapping="paper")
-    measure("bicubic_paper_map_x3_u8_rgba", lambda: u8, (12288, 12288, 4), "bicubic", mapping="paper")
-    del fld, unit, u8
-    measure("c1_bilinear_x2_u8_512", lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev),
-            (1024, 1024), "bilinear", all_kinds=True)
-    measure("c1_bilinear_x2_u8_512_unrotated",
-            lambda: torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev), (1024, 1024), "bilinear",
-            rotate=False, all_kinds=True)
-    measure("c4_bilinear_x2_f32_nchw_fwd", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
-            (32, 3, 2048, 2048), "bilinear", layout="nchw")
-    # C4 adjoint (exact x2 float32: register walk), and the owner-computes
-    # kernel: float16 gradients at x2, float32 at a non-dyadic scale
-    def adjoint(name, g_shape, in_hw, mode, dtype):
+        for direction, n, tag in [("x2", 8192, "x2"), ("x0.5", 2048, "x05")]:
+            measure("C2", f"bicubic_{direction}_{dname}_rgba", lambda t=t: t, (n, n, 4), "bicubic",
+                    profile=f"c2_bicubic_{tag}_{dname}_rgba.md")
+    if breadth:
+        measure("breadth", "nearest_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "nearest")
+        measure("breadth", "bicubic_aa_x0.5_u8_rgba", lambda: u8, (2048, 2048, 4), "bicubic_aa")
+        measure("breadth", "bilinear_aa_x0.25_u8_rgba", lambda: u8, (1024, 1024, 4), "bilinear_aa")
+        measure("breadth", "bilinear_paper_map_x2_u8_rgba", lambda: u8, (8192, 8192, 4), "bilinear",
+                mapping="paper")
+        measure("breadth", "bicubic_paper_map_x3_u8_rgba", lambda: u8, (12288, 12288, 4), "bicubic",
+                mapping="paper")
+    del unit, u8
+    torch.cuda.empty_cache()
+    measure("C4", "bilinear_x2_f32_nchw_forward", lambda: torch.randn((32, 3, 1024, 1024), device=dev),
+            (32, 3, 2048, 2048), "bilinear", layout="nchw", profile="c4_bilinear_x2_f32_forward.md")
+
+    # the adjoint: float32 (the configuration); with breadth, float16
+    # gradients and a non-dyadic scale (owner-computes kernel)
+    def adjoint(group, name, g_shape, in_hw, mode, dtype, profile=None):
         g = torch.randn(g_shape, device=dev).to(dtype)
         gs = torch.empty(g_shape[:2] + in_hw, device=dev, dtype=dtype)
 
@@ -620,20 +663,25 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
         wall, ms = time_launches(bwd, 1, 20, 3, torch)
         k_s = sum(ms) / len(ms) / 1e3
         alg = (g.numel() + gs.numel()) * g.element_size()
-        out[name] = {"ms": round(k_s * 1e3, 4), "gbs": round(alg / k_s / 1e9, 1),
-                     "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4),
-                     "gpixel_s": round(gs.numel() / k_s / 1e9, 2)}
+        out[group][name] = {
+            "alg_bytes": alg, "kernel_us": round(k_s * 1e6, 2), "gbs": round(alg / k_s / 1e9, 1),
+            "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4), "gpixel_s": round(gs.numel() / k_s / 1e9, 2),
+            **profile_fields(profile, alg)}
         if cpu:
             rate, used, t = cpu_baseline_adjoint(g, in_hw[0], in_hw[1], mode)
-            out[name].update({"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
-                              "cpu_sample": f"{used} whole planes"})
-        log(f"extra {name}: {out[name]}")
+            out[group][name].update({"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
+                                     "cpu_sample": f"{used} whole planes"})
+        log(f"{group} {name}: {out[group][name]}")
         del g, gs
         torch.cuda.empty_cache()
 
-    adjoint("c4_bilinear_x2_f32_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear", torch.float32)
-    adjoint("bilinear_x2_f16_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear", torch.float16)
-    adjoint("bicubic_x1.5_f32_nchw_adjoint", (32, 3, 1536, 1536), (1024, 1024), "bicubic", torch.float32)
+    adjoint("C4", "bilinear_x2_f32_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear", torch.float32,
+            profile="c4_bilinear_x2_f32_adjoint.md")
+    if breadth:
+        adjoint("breadth", "bilinear_x2_f16_nchw_adjoint", (32, 3, 2048, 2048), (1024, 1024), "bilinear",
+                torch.float16)
+        adjoint("breadth", "bicubic_x1.5_f32_nchw_adjoint", (32, 3, 1536, 1536), (1024, 1024), "bicubic",
+                torch.float32)
     # C5: 16384^2 FP16 -> 32768^2, whole image and 16 row bands
     src = torch.clamp(fields.smooth_field_torch(16384, 16384, 1, 1005, dev)[:, :, 0] / 255.0, 0, 1).half()
     dst = torch.empty((32768, 32768), dtype=torch.float16, device=dev)
@@ -655,12 +703,15 @@ def extras(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = True
     whole = ev[0].elapsed_time(ev[1]) / 3 / 1e3
     bands = ev[2].elapsed_time(ev[3]) / 1e3
     alg = (src.numel() + dst.numel()) * 2
-    out["c5_bicubic_x2_f16_16384"] = {"whole_ms": round(whole * 1e3, 3), "bands16_ms": round(bands * 1e3, 3),
-                                      "gbs": round(alg / whole / 1e9, 1),
-                                      "hbm_frac": round(alg / whole / 1e9 / HBM_PEAK_GBS, 4),
-                                      "bands_bitwise_equal": bool(torch.equal(dst, dst_b)),
-                                      **oracle_rate(src, (32768, 32768), "bicubic", "hwc")}
-    log(f"extra C5: {out['c5_bicubic_x2_f16_16384']}")
+    out["C5"]["bicubic_x2_f16_16384"] = {
+        "alg_bytes": alg, "kernel_us": round(whole * 1e6, 1), "bands16_us": round(bands * 1e6, 1),
+        "gbs": round(alg / whole / 1e9, 1), "hbm_frac": round(alg / whole / 1e9 / HBM_PEAK_GBS, 4),
+        "bands_gbs": round(alg / bands / 1e9, 1), "bands_bitwise_equal": bool(torch.equal(dst, dst_b)),
+        **profile_fields("c5_bicubic_x2_f16_16384.md", alg),
+        **oracle_rate(src, (32768, 32768), "bicubic", "hwc")}
+    log(f"C5: {out['C5']['bicubic_x2_f16_16384']}")
+    del src, dst, dst_b
+    torch.cuda.empty_cache()
     return out
 
 
@@ -798,7 +849,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched comparison")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch shape")
-    ap.add_argument("--extras", action="store_true", help="also time the other workloads")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the other configurations (C1, C2 storage types and x0.5, C4, C5)")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the other filters and maps and two more adjoints")
     ap.add_argument("--tile", type=str, default=None,
                     help="fixed launch shape KIND,BW,BH,PPX,PPY[,ORDER] (kind 1 gather, 2 strip) instead of tuning")
     ap.add_argument("--calibrate", action="store_true",
@@ -856,7 +910,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": "bicubic (Keys a=-0.5) x2 resize, 4096x4096 RGBA uint8 -> 8192x8192, "
                                "half-pixel centres, clamp-to-edge, float32 weights/accumulation",
@@ -872,8 +926,9 @@ def main():
     if not args.no_cpu:
         log("timing the FP64 CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(h["src_host"])
-    if args.extras:
-        result["extras"] = extras(torch, xr, fields, cpu=not args.no_cpu)
+    if not args.no_configs:
+        result["configs"] = configs(torch, xr, fields, cpu=not args.no_cpu, breadth=args.extras)
+        result["configs"]["C3"] = "the batched entry"
     print(json.dumps(result), flush=True)
 
 
