@@ -295,7 +295,10 @@ int xr_resize_backward(const xr_image *grad_dst, const xr_image *grad_src, int32
  * pairs must have the same filter key, sizes, dtype and channels. Writes the
  * fastest shape to *best and its time per launch in ms to *best_ms (either
  * may be NULL) and remembers it for later XR_KERNEL_AUTO calls with the same
- * key (filter, dtype, channels, scale class). Overwrites the dsts.
+ * key (filter, dtype, channels, the scale class of each axis: x2, identity,
+ * other up, x0.5, other down; and the size class of the output's
+ * width x height x planes pixels: up to 2^16, 2^20, 2^24, 2^26, beyond).
+ * Overwrites the dsts.
  * candidates = NULL uses the built-in candidate list. Synchronises the
  * stream; NOT capturable.
  * xr_tune_candidates: copies up to `cap` built-in candidates for the given
@@ -308,13 +311,28 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
                            int32_t in_h, int32_t out_w, int32_t out_h, xr_tile *out, int32_t cap);
 
 /*
- * The shape XR_KERNEL_AUTO resolves to for a key: the tuned one if
- * xr_autotune (or xr_set_tile) stored one, else the built-in default.
+ * The shape XR_KERNEL_AUTO resolves to for a key (images of one plane): the
+ * tuned one if xr_autotune (or xr_set_tile) stored one, else the built-in
+ * default. xr_set_tile with kernel XR_KERNEL_AUTO forgets the key's shape.
  */
 int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
                 int32_t out_w, int32_t out_h, xr_tile *out);
 int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
                 int32_t out_w, int32_t out_h, const xr_tile *tile);
+
+/*
+ * Persisted launch shapes (the tuned table of xr_autotune / xr_set_tile).
+ * xr_tune_save writes the table to the text file `path`, headed by the
+ * current device's architecture name, its compute-unit count and the
+ * library's build identity (a hash of its kernel sources).
+ * xr_tune_load merges the shapes of such a file into the table and sets
+ * *n_loaded to their number; a file of another architecture, CU count or
+ * build loads nothing (*n_loaded = 0, XR_OK), so a stale cache is ignored.
+ * Both query the current device (HIP calls); XR_ERR_ARG when the file cannot
+ * be written or read.
+ */
+int xr_tune_save(const char *path);
+int xr_tune_load(const char *path, int32_t *n_loaded);
 
 /*
  * Host-side geometry (no HIP call; usable without a GPU).

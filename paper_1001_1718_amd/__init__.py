@@ -11,6 +11,7 @@ Layouts: ``"hwc"`` tensors are (H, W), (H, W, C) or (P, H, W, C) with C in
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -263,6 +264,19 @@ def autotune(src, dst, mode="bicubic", layout="hwc", candidates=None, reps: int 
                           ctypes.byref(best), ctypes.byref(ms), _stream_handle(srcs[0], stream)),
           "autotune")
     return best, float(ms.value)
+
+
+def tune_save(path: str) -> None:
+    """Write the tuned launch shapes to `path` (xr_tune_save)."""
+    check(lib.xr_tune_save(os.fsencode(path)), "tune_save")
+
+
+def tune_load(path: str) -> int:
+    """Merge the launch shapes of `path` if it was written for this GPU and
+    build (xr_tune_load); returns how many were loaded."""
+    n = ctypes.c_int32()
+    check(lib.xr_tune_load(os.fsencode(path), ctypes.byref(n)), "tune_load")
+    return int(n.value)
 
 
 def tune_candidates(mode, dtype_code, channels, in_w, in_h, out_w, out_h):

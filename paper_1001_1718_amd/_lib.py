@@ -93,6 +93,8 @@ def _load():
         "xr_batch_prepare": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, vp, sz, vp]),
         "xr_resize_batched": (ctypes.c_int, [vp, i32, vp]),
         "xr_resize_batched_static": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, vp]),
+        "xr_tune_save": (ctypes.c_int, [ctypes.c_char_p]),
+        "xr_tune_load": (ctypes.c_int, [ctypes.c_char_p, pi32]),
         "xr_batch_autotune": (ctypes.c_int, [ctypes.POINTER(XrJob), i32, ptile, i32, i32, i32, vp, sz,
                                              ptile, ctypes.POINTER(ctypes.c_float), vp]),
         "xr_resize_backward": (ctypes.c_int, [pimg, pimg, i32, vp]),

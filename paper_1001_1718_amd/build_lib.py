@@ -9,6 +9,7 @@ package loads the library this script builds.
 from __future__ import annotations
 
 import concurrent.futures
+import hashlib
 import os
 import shutil
 import subprocess
@@ -26,7 +27,7 @@ SOURCES = ["xr_api.cpp", "xr_forward.hip", "xr_backward.hip"]
 #   float32 evaluation order (and the result) is fixed by the source.
 # -packed-fp32-ops: no packed FP32 instructions are generated.
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
-DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off", "-munsafe-fp-atomics",
+DEVICE = [f"--offload-arch={ARCH}", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
@@ -37,9 +38,21 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def build_id() -> str:
+    """Hash of every library source: the identity of a build's kernels, kept
+    with persisted launch shapes so that a rebuilt library ignores shapes
+    tuned on other kernels."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp", ".h", ".cpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *COMMON, *DEVICE, f'-DXR_BUILD_ID="{build_id()}"', "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

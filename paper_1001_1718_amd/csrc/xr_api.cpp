@@ -17,6 +17,11 @@
 #include "../../include/xresize.h"
 #include "xr_internal.h"
 
+// Identity of the kernel build (a hash of the kernel sources, set by the build).
+#ifndef XR_BUILD_ID
+#define XR_BUILD_ID "unversioned"
+#endif
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -278,12 +283,24 @@ int scale_class(int32_t n_in, int32_t n_out)
     return 4;
 }
 
-using TuneKey = std::tuple<int, int, int, int, int>;
+// size class of the output, out_w x out_h x planes pixels: 0 up to 2^16
+// (256^2), 1 up to 2^20 (1024^2), 2 up to 2^24 (4096^2), 3 up to 2^26
+// (8192^2), 4 beyond. A shape tuned on a large output fills the GPU with
+// long strips that a small one would leave mostly idle.
+int size_class(int32_t out_w, int32_t out_h, int32_t planes)
+{
+    const int64_t px = static_cast<int64_t>(out_w) * out_h * std::max(planes, 1);
+    return px <= (int64_t(1) << 16) ? 0 : px <= (int64_t(1) << 20) ? 1 : px <= (int64_t(1) << 24) ? 2
+                                                                 : px <= (int64_t(1) << 26) ? 3 : 4;
+}
+
+using TuneKey = std::tuple<int, int, int, int, int, int>;
 
 TuneKey tune_key(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, int32_t in_h,
-                 int32_t out_w, int32_t out_h)
+                 int32_t out_w, int32_t out_h, int32_t planes)
 {
-    return TuneKey(filter, dtype, channels, scale_class(in_w, out_w), scale_class(in_h, out_h));
+    return TuneKey(filter, dtype, channels, scale_class(in_w, out_w), scale_class(in_h, out_h),
+                   size_class(out_w, out_h, planes));
 }
 
 std::mutex g_tune_mu;
@@ -460,7 +477,7 @@ xr_tile resolve_tile(const xr_tile *tile, int32_t filter, const xr_image &src, c
     if (tile && tile->kernel != XR_KERNEL_AUTO)
         return *tile;
     const TuneKey key = tune_key(filter, src.dtype, src.channels, src.width, src.height, dst.width,
-                                 dst.height);
+                                 dst.height, dst.planes);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find(key);
     // a tuned LDS shape applies only to sources it can stage (alignment is
@@ -539,6 +556,25 @@ xr_tile batch_default_tile(int32_t dtype)
     if (it != g_batch_tuned.end())
         return it->second;
     return xr_tile{XR_KERNEL_STRIP, 256, 1, 0, 14, 0};
+}
+
+// The current device's architecture name and compute-unit count (the key of
+// persisted launch shapes).
+int device_identity(std::string &arch, int &cus)
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess)
+        e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess)
+        return fail_hip(e, "device query");
+    arch = prop.gcnArchName;
+    for (char &c : arch)
+        if (c == ' ')
+            c = '_';
+    cus = prop.multiProcessorCount;
+    return XR_OK;
 }
 
 // ---- the batched launch without allocation ------------------------------
@@ -1154,7 +1190,7 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[tune_key(filter, src->dtype, src->channels, src->width, src->height, dst->width,
-                         dst->height)] = cand[best_k];
+                         dst->height, dst->planes)] = cand[best_k];
     }
     if (best)
         *best = cand[best_k];
@@ -1177,7 +1213,7 @@ int xr_get_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
     if (in_w < 1 || in_h < 1 || out_w < 1 || out_h < 1)
         return fail(XR_ERR_SHAPE, "sizes must be positive");
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    auto it = g_tuned.find(tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h));
+    auto it = g_tuned.find(tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h, 1));
     *out = it != g_tuned.end() ? it->second
                                : default_tile(channels, in_w, in_h, out_w, out_h, out_h, 1);
     return XR_OK;
@@ -1196,7 +1232,7 @@ int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
         return fail(XR_ERR_CHANNELS, "channels = %d", channels);
     if (in_w < 1 || in_h < 1 || out_w < 1 || out_h < 1)
         return fail(XR_ERR_SHAPE, "sizes must be positive");
-    const TuneKey key = tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h);
+    const TuneKey key = tune_key(filter, dtype, channels, in_w, in_h, out_w, out_h, 1);
     std::lock_guard<std::mutex> lock(g_tune_mu);
     if (tile->kernel == XR_KERNEL_AUTO) {
         g_tuned.erase(key);
@@ -1208,6 +1244,69 @@ int xr_set_tile(int32_t filter, int32_t dtype, int32_t channels, int32_t in_w, i
     if (rc)
         return rc;
     g_tuned[key] = *tile;
+    return XR_OK;
+}
+
+int xr_tune_save(const char *path)
+{
+    if (!path)
+        return fail(XR_ERR_NULL, "path is NULL");
+    std::string arch;
+    int cus = 0;
+    int rc = device_identity(arch, cus);
+    if (rc)
+        return rc;
+    FILE *f = std::fopen(path, "w");
+    if (!f)
+        return fail(XR_ERR_ARG, "cannot write %s", path);
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    std::fprintf(f, "xresize-tiles 1\narch %s cus %d build %s\n", arch.c_str(), cus, XR_BUILD_ID);
+    for (const auto &kv : g_tuned) {
+        const TuneKey &k = kv.first;
+        const xr_tile &t = kv.second;
+        std::fprintf(f, "%d %d %d %d %d %d  %d %d %d %d %d %d\n", std::get<0>(k), std::get<1>(k), std::get<2>(k),
+                     std::get<3>(k), std::get<4>(k), std::get<5>(k), t.kernel, t.block_w, t.block_h, t.ppt_x,
+                     t.ppt_y, t.order);
+    }
+    const bool ok = std::fclose(f) == 0;
+    return ok ? XR_OK : fail(XR_ERR_ARG, "writing %s failed", path);
+}
+
+int xr_tune_load(const char *path, int32_t *n_loaded)
+{
+    if (!path || !n_loaded)
+        return fail(XR_ERR_NULL, "path or n_loaded is NULL");
+    *n_loaded = 0;
+    std::string arch;
+    int cus = 0;
+    int rc = device_identity(arch, cus);
+    if (rc)
+        return rc;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return fail(XR_ERR_ARG, "cannot read %s", path);
+    char f_arch[256] = {0}, f_build[128] = {0};
+    int version = 0, f_cus = 0;
+    const bool header = std::fscanf(f, "xresize-tiles %d arch %255s cus %d build %127s", &version, f_arch,
+                                    &f_cus, f_build) == 4;
+    // shapes tuned on another GPU model, CU count or build of the kernels
+    // are not used
+    if (!header || version != 1 || arch != f_arch || cus != f_cus || std::strcmp(f_build, XR_BUILD_ID) != 0) {
+        std::fclose(f);
+        return XR_OK;
+    }
+    int v[12];
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    while (std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %d %d", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5], &v[6],
+                       &v[7], &v[8], &v[9], &v[10], &v[11]) == 12) {
+        const xr_tile t{v[6], v[7], v[8], v[9], v[10], v[11]};
+        if (!valid_filter(v[0]) || elem_size(v[1]) == 0 || (v[2] != 1 && v[2] != 4) ||
+            check_tile(t, v[1], v[2]) != XR_OK)
+            continue;
+        g_tuned[TuneKey(v[0], v[1], v[2], v[3], v[4], v[5])] = t;
+        ++*n_loaded;
+    }
+    std::fclose(f);
     return XR_OK;
 }
 

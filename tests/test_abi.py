@@ -282,3 +282,21 @@ def test_get_set_tile_roundtrip():
     assert xr.get_tile(*key).as_tuple() == default.as_tuple()
     with pytest.raises(xr.XResizeError):
         xr.set_tile(*key, xr.tile(xr.XR_KERNEL_STRIP, 100, 1, 8, 16))
+
+
+def test_tuned_shape_keyed_by_output_size():
+    """A shape stored for a large output is not used for a small output of the
+    same filter, storage, channels and scale, and vice versa; outputs in the
+    same size class share it."""
+    big = ("bicubic", xr.XR_U8, 4, 4096, 4096, 8192, 8192)      # 2^26 px: class 3
+    small = ("bicubic", xr.XR_U8, 4, 64, 64, 128, 128)          # 2^14 px: class 0
+    near = ("bicubic", xr.XR_U8, 4, 3000, 3000, 6000, 6000)     # class 3 too
+    d_small = xr.get_tile(*small).as_tuple()
+    t = xr.tile(xr.XR_KERNEL_STRIP, 512, 1, 2, 24)
+    xr.set_tile(*big, t)
+    try:
+        assert xr.get_tile(*big).as_tuple() == t.as_tuple()
+        assert xr.get_tile(*near).as_tuple() == t.as_tuple()
+        assert xr.get_tile(*small).as_tuple() == d_small
+    finally:
+        xr.set_tile(*big, xr.tile(xr.XR_KERNEL_AUTO))
