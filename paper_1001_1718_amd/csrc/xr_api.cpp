@@ -663,7 +663,7 @@ int build_batch(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, unsigne
     };
     const auto kind_of = [&](const xr_job &j) {
         const int32_t taps = j.filter == XR_BICUBIC ? 4 : 2;
-        if (j.src.width < taps || j.dst.width < xr::batch_ppx(dtype, j.src.channels))
+        if (j.src.width < taps || j.dst.width < xr::batch_ppx(j.filter, dtype, j.src.channels))
             return xr::kBatchNarrow;
         return fc_of(j);
     };
@@ -705,7 +705,7 @@ int build_batch(const xr_job *jobs, int32_t n_jobs, const xr_tile *tile, unsigne
         strip = std::min<int64_t>(strip, std::max<int64_t>(1, max_rows * j.dst.height / j.src.height));
         b.strip_h = static_cast<int32_t>(strip);
         const int64_t tile_w =
-            static_cast<int64_t>(t.block_w) * (kind == xr::kBatchNarrow ? 1 : xr::batch_ppx(dtype, j.src.channels));
+            static_cast<int64_t>(t.block_w) * (kind == xr::kBatchNarrow ? 1 : xr::batch_ppx(j.filter, dtype, j.src.channels));
         const int64_t tile_h = static_cast<int64_t>(t.block_h) * b.strip_h;
         b.tiles_x = static_cast<int32_t>((j.dst.width + tile_w - 1) / tile_w);
         b.tiles_y = static_cast<int32_t>((j.dst.rows + tile_h - 1) / tile_h);

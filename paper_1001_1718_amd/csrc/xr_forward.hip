@@ -1672,7 +1672,7 @@ struct SrcWalk : ColTaps<FILTER, T, C, PPX> {
 template <int FILTER, typename T, int C>
 __global__ void __launch_bounds__(256) k_batch_walk(unsigned char *ws, int32_t kind)
 {
-    constexpr int PPX = batch_ppx(DType<T>::kCode, C);
+    constexpr int PPX = batch_ppx(FILTER == kBicubic ? XR_BICUBIC : XR_BILINEAR, DType<T>::kCode, C);
     using W = SrcWalk<FILTER, T, C, PPX>;
     __shared__ typename W::WRow table[4][kBatchMaxStrip];
     __shared__ uint32_t s_tile;

@@ -78,11 +78,13 @@ struct alignas(K * 4) BatchWeights {
     float w[K];
 };
 
-// Output columns per thread of the batched walk, per storage type and channel
-// count: runs of 8 to 16 bytes per thread (the narrow kind: one column).
-constexpr int32_t batch_ppx(int32_t dtype, int32_t channels)
+// Output columns per thread of the batched walk, per filter, storage type and
+// channel count: 16-byte runs for bilinear, 8 to 16 for bicubic (whose four
+// tap rows per column would leave fewer waves with 16-byte uint8 runs); the
+// narrow kind takes one column.
+constexpr int32_t batch_ppx(int32_t filter, int32_t dtype, int32_t channels)
 {
-    return dtype == XR_U8 ? (channels == 1 ? 8 : 2)
+    return dtype == XR_U8 ? (channels == 1 ? (filter == XR_BILINEAR ? 16 : 8) : (filter == XR_BILINEAR ? 4 : 2))
          : dtype == XR_F16 ? (channels == 1 ? 8 : 2)
                            : (channels == 1 ? 4 : 1);
 }
