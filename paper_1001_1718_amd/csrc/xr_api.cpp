@@ -1011,8 +1011,10 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
                 out[k] = c[k];
         return static_cast<int32_t>(c.size());
     }
-    const int ppx_c4[3] = {2, 4, 8};
-    const int ppx_c1[3] = {4, 8, 16};
+    // one RGBA column per thread only for the exact x0.5 walk (more waves on
+    // its quarter-size output, so taller strips with less halo)
+    const int ppx_c4[4] = {2, 4, 8, 1};
+    const int ppx_c1[4] = {4, 8, 16, 0};
     const int *ppx_list = channels == 4 ? ppx_c4 : ppx_c1;
     const int blocks[][2] = {{64, 4}, {128, 2}, {256, 1}, {256, 2}, {512, 1}};
     const bool x2 = out_w == 2 * in_w && out_h == 2 * in_h;
@@ -1022,14 +1024,19 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
         // group of its loop); the exact x0.5 walk: strips of an even number
         // of rows; one workgroup order
         const int x2_rows[] = {8, 16, 24, 32, 48, 64};
-        const int x05_rows[] = {2, 4, 6, 8, 12, 16};
-        for (int k = 0; k < 3; ++k) {
+        const int x05_rows[] = {2, 4, 6, 8, 12, 16, 24, 32};
+        for (int k = 0; k < (x05 ? 4 : 3); ++k) {
             const int ppx = ppx_list[k];
             if (!xr::strip_ppx_supported(dtype, channels, ppx))
                 continue;
-            for (const auto &b : blocks)
-                for (int ppy : (x2 ? x2_rows : x05_rows))
-                    c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
+            for (const auto &b : blocks) {
+                if (x2)
+                    for (int ppy : x2_rows)
+                        c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
+                else
+                    for (int ppy : x05_rows)
+                        c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
+            }
         }
         if (out)
             for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)

@@ -1921,7 +1921,7 @@ bool strip_ppx_supported(int32_t dtype, int32_t channels, int32_t ppx)
 {
     (void)dtype;
     if (channels == 4)
-        return ppx == 2 || ppx == 4 || ppx == 8;
+        return ppx == 1 || ppx == 2 || ppx == 4 || ppx == 8;
     return ppx == 4 || ppx == 8 || ppx == 16;
 }
 
@@ -1967,7 +1967,7 @@ hipError_t launch_lds(const ResizeArgs &a, const xr_tile &tile, hipStream_t stre
 template <typename T, int C, int PPX>
 constexpr bool x2_ppx_ok()
 {
-    return ((PPX / 2) * Pix<T, C>::kBytes) % 4 == 0 && PPX * Pix<T, C>::kBytes <= 64;
+    return PPX % 2 == 0 && ((PPX / 2) * Pix<T, C>::kBytes) % 4 == 0 && PPX * Pix<T, C>::kBytes <= 64;
 }
 
 // Strips of 2 np output rows, np = ppt_y / 2 rounded up to a multiple of 4
@@ -2047,6 +2047,7 @@ hipError_t launch_typed(const ResizeArgs &a, const xr_tile &tile, int32_t mode, 
         return hipGetLastError();
     if constexpr (C == 4) {
         switch (tile.ppt_x) {
+            XR_STRIP_CASE(1)
             XR_STRIP_CASE(2)
             XR_STRIP_CASE(4)
             XR_STRIP_CASE(8)
