@@ -433,7 +433,7 @@ def cpu_baseline(src_host, target_s: float = 10.0):
 
 
 def touched_rows(n_in: int, n_out: int, taps: int) -> int:
-    """Source rows (or columns) that some output row reads: the union over
+    """Source rows (or columns) that some output row (column) reads: the union over
     output indices y of the clamped taps y0 - lo .. y0 - lo + K - 1 with
     y0 = floor((2 y + 1) n_in / (2 n_out) - 1/2) (eqs. 1-4). Every row when
     the tap windows overlap or touch; fewer when shrinking by more than K."""
@@ -448,11 +448,13 @@ def touched_rows(n_in: int, n_out: int, taps: int) -> int:
 
 def batch_alg_bytes(jobs) -> int:
     """Algorithmic bytes of a batch: every output pixel written once and every
-    source row that some output row reads (touched_rows) read once."""
+    source pixel that some output pixel reads read once (the touched rows
+    times the touched columns, touched_rows on each axis)."""
     total = 0
     for j in jobs:
         taps = 4 if j.filter == 1 else 2
-        total += touched_rows(j.in_h, j.out_h, taps) * j.in_w * j.channels + j.out_h * j.out_w * j.channels
+        touched = touched_rows(j.in_h, j.out_h, taps) * touched_rows(j.in_w, j.out_w, taps)
+        total += touched * j.channels + j.out_h * j.out_w * j.channels
     return total
 
 
