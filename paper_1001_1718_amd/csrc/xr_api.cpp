@@ -1022,21 +1022,22 @@ int32_t xr_tune_candidates(int32_t filter, int32_t dtype, int32_t channels, int3
     if ((x2 || x05) && filter != XR_NEAREST) {
         // the exact x2 walk: strips of 8 m rows (m pairs of rows per 4-row
         // group of its loop); the exact x0.5 walk: strips of an even number
-        // of rows; one workgroup order
+        // of rows; both workgroup orders
         const int x2_rows[] = {8, 16, 24, 32, 48, 64};
         const int x05_rows[] = {2, 4, 6, 8, 12, 16, 24, 32};
         for (int k = 0; k < (x05 ? 4 : 3); ++k) {
             const int ppx = ppx_list[k];
             if (!xr::strip_ppx_supported(dtype, channels, ppx))
                 continue;
-            for (const auto &b : blocks) {
-                if (x2)
-                    for (int ppy : x2_rows)
-                        c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
-                else
-                    for (int ppy : x05_rows)
-                        c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, 0});
-            }
+            for (const auto &b : blocks)
+                for (int order = 0; order < 2; ++order) {
+                    if (x2)
+                        for (int ppy : x2_rows)
+                            c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, order});
+                    else
+                        for (int ppy : x05_rows)
+                            c.push_back(xr_tile{XR_KERNEL_STRIP, b[0], b[1], ppx, ppy, order});
+                }
         }
         if (out)
             for (int32_t k = 0; k < cap && k < static_cast<int32_t>(c.size()); ++k)

@@ -1093,16 +1093,17 @@ constexpr int kX2Prefetch = 1;
 // Strip s of np pairs covers logical output rows [2 s np - 1, 2 (s+1) np - 1);
 // threadIdx.y picks one of blockDim.y consecutive strips from s_first on.
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(512) k_x2(ResizeArgs a, int32_t np, int32_t s_first)
+__global__ void __launch_bounds__(512) k_x2(ResizeArgs a, int32_t np, int32_t s_first, int32_t order)
 {
+    int32_t bx, by;
+    tile_coords(order, bx, by);
     using W = X2Walk<FILTER, T, C, PPX, kX2Prefetch>;
     constexpr int K = W::K, LO = W::LO, SPAN = W::SPAN, PB = W::PB;
-    const int32_t col0 =
-        (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
+    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
     if (!RunStore<T, C, PPX>::kExchange && col0 >= a.out_w)  // (an exchange needs every lane)
         return;
-    const int32_t s =
-        s_first + __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y));
+    const int32_t s = s_first + __builtin_amdgcn_readfirstlane(by * static_cast<int32_t>(blockDim.y) +
+                                                               static_cast<int32_t>(threadIdx.y));
     const int32_t ys = 2 * s * np - 1;
     const int32_t y_lo = max(ys, max(a.dst_row0, 0));
     const int32_t y_hi = min(ys + 2 * np, min(a.dst_row0 + a.dst_rows, a.out_h));
@@ -1280,16 +1281,17 @@ constexpr int kX05Prefetch = 1;
 // Strip s covers logical output rows [s nr, (s + 1) nr); threadIdx.y picks
 // one of blockDim.y consecutive strips from s_first on.
 template <int FILTER, typename T, int C, int PPX>
-__global__ void __launch_bounds__(512) k_x05(ResizeArgs a, int32_t nr, int32_t s_first)
+__global__ void __launch_bounds__(512) k_x05(ResizeArgs a, int32_t nr, int32_t s_first, int32_t order)
 {
+    int32_t bx, by;
+    tile_coords(order, bx, by);
     using W = D2Walk<FILTER, T, C, PPX, kX05Prefetch>;
     constexpr int K = W::K, LO = W::LO, NEED = W::NEED, PB = W::PB;
-    const int32_t col0 =
-        (static_cast<int32_t>(blockIdx.x * blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
+    const int32_t col0 = (bx * static_cast<int32_t>(blockDim.x) + static_cast<int32_t>(threadIdx.x)) * PPX;
     if (!RunStore<T, C, PPX>::kExchange && col0 >= a.out_w)  // (an exchange needs every lane)
         return;
-    const int32_t s =
-        s_first + __builtin_amdgcn_readfirstlane(static_cast<int32_t>(blockIdx.y * blockDim.y + threadIdx.y));
+    const int32_t s = s_first + __builtin_amdgcn_readfirstlane(by * static_cast<int32_t>(blockDim.y) +
+                                                               static_cast<int32_t>(threadIdx.y));
     const int32_t ys = s * nr;
     const int32_t y_lo = max(ys, max(a.dst_row0, 0));
     const int32_t y_hi = min(ys + nr, min(a.dst_row0 + a.dst_rows, a.out_h));
@@ -1988,7 +1990,8 @@ hipError_t launch_x2(const ResizeArgs &a, const xr_tile &tile, hipStream_t strea
     const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
                     static_cast<uint32_t>((strips + tile.block_h - 1) / tile.block_h), a.planes);
     const size_t lds = run_store_lds<T, C, PPX>(tile.block_w * tile.block_h);
-    hipLaunchKernelGGL((k_x2<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(np), static_cast<int32_t>(s_first));
+    hipLaunchKernelGGL((k_x2<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(np),
+                       static_cast<int32_t>(s_first), tile.order);
     return hipGetLastError();
 }
 
@@ -2009,7 +2012,8 @@ hipError_t launch_x05(const ResizeArgs &a, const xr_tile &tile, hipStream_t stre
     const dim3 grid((a.out_w + cols_per_block - 1) / cols_per_block,
                     static_cast<uint32_t>((strips + tile.block_h - 1) / tile.block_h), a.planes);
     const size_t lds = run_store_lds<T, C, PPX>(tile.block_w * tile.block_h);
-    hipLaunchKernelGGL((k_x05<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(nr), static_cast<int32_t>(s_first));
+    hipLaunchKernelGGL((k_x05<FILTER, T, C, PPX>), grid, block, lds, stream, a, static_cast<int32_t>(nr),
+                       static_cast<int32_t>(s_first), tile.order);
     return hipGetLastError();
 }
 

@@ -454,15 +454,17 @@ EXACT_SHAPES = [
 def test_exact_ratio_walks_every_width(shape, dtype, channels, mode):
     """The exact x2 and x0.5 walks with every built run width (direct and
     LDS-exchanged run stores, edge runs rebuilt in registers or loaded pixel
-    by pixel) and strip heights that split the image unevenly: bitwise equal
+    by pixel), strip heights that split the image unevenly and both workgroup
+    orders: bitwise equal
     to each other and to the one-pixel gather, and within the oracle rule."""
     (in_h, in_w), (out_h, out_w) = shape
     img = _input(dtype, in_h, in_w, channels, seed=in_h * 31 + in_w * 7 + channels)
     ref = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_GATHER, 64, 1))
     compare(ref, img, out_h, out_w, MODES[mode], what=f"{shape} {mode}")
-    widths = (2, 4, 8) if channels == 4 else (4, 8, 16)
+    widths = (1, 2, 4, 8) if channels == 4 else (4, 8, 16)
     for ppx in widths:
         for bw, bh, ppy in ((64, 1, 8), (128, 2, 16), (64, 4, 2)):
-            got = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_STRIP, bw, bh, ppx, ppy))
-            np.testing.assert_array_equal(got.view(np.uint8), ref.view(np.uint8),
-                                          err_msg=f"ppx {ppx} block {bw}x{bh} rows {ppy}")
+            for order in (0, 1):
+                got = _gpu(img, out_h, out_w, mode, xr.tile(xr.XR_KERNEL_STRIP, bw, bh, ppx, ppy, order))
+                np.testing.assert_array_equal(got.view(np.uint8), ref.view(np.uint8),
+                                              err_msg=f"ppx {ppx} block {bw}x{bh} rows {ppy} order {order}")
