@@ -561,7 +561,9 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
     batch (C1, C2 in three storage types and both directions, C4 forward and
     adjoint, C5 whole and in row bands): per launch the algorithmic bytes,
     the mean kernel time from HIP events, GB/s and the fraction of the HBM
-    peak, the tuned launch shape, and the oracle's rate on a sample of the
+    peak (and that fraction at the per-launch time of a HIP graph replay,
+    graph_hbm_frac: per-launch events add microseconds of submission to the
+    small kernels), the tuned launch shape, and the oracle's rate on a sample of the
     same workload (about 1 s of host time; `cpu_mpx_s`, the cores it used and
     its sample) unless cpu is False. `profile` names the rocprofv3 summary in
     profiles/ of the configuration's kernel. With breadth, also the other
@@ -620,6 +622,7 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
             "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4), "gpixel_s": round(px / k_s / 1e9, 2),
             "tile": repr(tile), "buffers": n_buf,
             "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2), "graph_us": round(g_us, 2),
+            "graph_hbm_frac": round(alg / (g_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             **profile_fields(profile, alg),
             **oracle_rate(src0, out_hw, mode, layout, mapping)}
         log(f"{group} {name}: {out[group][name]}")
