@@ -734,6 +734,12 @@ def profile_workload(args, torch, xr, fields):
     dev = torch.device("cuda:0")
     name = args.profile
     steps = args.steps
+
+    def fix_tile(mode, dtype, channels, in_w, in_h, out_w, out_h):
+        if args.tile:
+            xr.set_tile(mode, dtype, channels, in_w, in_h, out_w, out_h,
+                        xr.tile(*(int(v) for v in args.tile.split(","))))
+
     if name == "copy":  # counter calibration: a plain 1 GiB device copy
         a = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -758,6 +764,9 @@ def profile_workload(args, torch, xr, fields):
         g = torch.randn((32, 3, 2048, 2048), device=dev)
         if name == "c4_fwd":
             y = torch.empty_like(g)
+            if args.tile:  # (a shape for 96 planes: stored by a one-candidate tuning)
+                xr.autotune([x], [y], "bilinear", layout="nchw", reps=1, groups=1,
+                            candidates=[xr.tile(*(int(v) for v in args.tile.split(",")))])
             launch = lambda i: xr.resize_into(x, y, "bilinear", layout="nchw")
         else:
             gx = torch.empty_like(x)
@@ -766,10 +775,12 @@ def profile_workload(args, torch, xr, fields):
     elif name == "c5":
         src = torch.clamp(fields.smooth_field_torch(16384, 16384, 1, 1005, dev)[:, :, 0] / 255.0, 0, 1).half()
         dst = torch.empty((32768, 32768), dtype=torch.float16, device=dev)
+        fix_tile("bicubic", xr.XR_F16, 1, 16384, 16384, 32768, 32768)
         launch, alg = (lambda i: xr.resize_into(src, dst, "bicubic")), (src.numel() + dst.numel()) * 2
     elif name == "c1":
         src = torch.randint(0, 256, (512, 512), dtype=torch.uint8, device=dev)
         dst = torch.empty((1024, 1024), dtype=torch.uint8, device=dev)
+        fix_tile("bilinear", xr.XR_U8, 1, 512, 512, 1024, 1024)
         launch, alg = (lambda i: xr.resize_into(src, dst, "bilinear")), 512 * 512 + 1024 * 1024
     else:  # C2: x2 / x05, storage u8 / f16 / f32, bicubic RGBA 4096^2
         direction, _, dname = name.partition("_")
@@ -783,9 +794,7 @@ def profile_workload(args, torch, xr, fields):
         n_buf = max(1, math.ceil(ROTATE_BYTES / (src.numel() * src.element_size() * (1 + (n / 4096) ** 2))))
         srcs = [src] + [src.clone() for _ in range(n_buf - 1)]
         dsts = [torch.empty((n, n, 4), dtype=src.dtype, device=dev) for _ in range(n_buf)]
-        if args.tile:
-            xr.set_tile("bicubic", xr._DTYPES[src.dtype], 4, 4096, 4096, n, n,
-                        xr.tile(*(int(v) for v in args.tile.split(","))))
+        fix_tile("bicubic", xr._DTYPES[src.dtype], 4, 4096, 4096, n, n)
         launch = lambda i: xr.resize_into(srcs[i % n_buf], dsts[i % n_buf], "bicubic")
         alg = (4096 * 4096 + n * n) * 4 * src.element_size()
     for i in range(3):
