@@ -165,7 +165,9 @@ def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
 def graph_steps(launch, n_buffers: int, steps: int, torch) -> float:
     """Wall seconds of exactly `steps` launches submitted as replays of one
     HIP graph holding the n_buffers rotating launches (any remainder eager),
-    bracketed by device synchronisation; one untimed replay first."""
+    bracketed by device synchronisation; one untimed replay first. The HIP
+    events recorded on the replaying stream around the same steps give
+    graph_steps.event_ms, their GPU time."""
     graph = torch.cuda.CUDAGraph()
     stream = torch.cuda.Stream()
     stream.wait_stream(torch.cuda.current_stream())
@@ -175,14 +177,18 @@ def graph_steps(launch, n_buffers: int, steps: int, torch) -> float:
                 launch(i)
     torch.cuda.current_stream().wait_stream(stream)
     graph.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record()
     for _ in range(steps // n_buffers):
         graph.replay()
     for i in range(steps % n_buffers):
         launch(i)
+    e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    graph_steps.event_ms = e0.elapsed_time(e1)
     del graph
     return wall
 
@@ -217,7 +223,8 @@ def group_stats(ms, group: int = 100):
         groups = [ms]
     means = [sum(g) / len(g) for g in groups]
     return {"groups": len(groups), "median_ms": statistics.median(means), "min_ms": min(means),
-            "max_ms": max(means), "mean_ms": sum(ms) / len(ms)}
+            "max_ms": max(means), "mean_ms": sum(ms) / len(ms),
+            "group_means_ms": [round(m, 5) for m in means]}
 
 
 def headline(args, torch, xr, fields):
@@ -258,6 +265,11 @@ def headline(args, torch, xr, fields):
     wall = graph_steps(launch, n_buf, args.steps, torch)
     out_px = out_hw * out_hw
     value = out_px * args.steps / wall / 1e9
+    # the roofline's launch time: the mean of the HIP event pairs around each
+    # eager launch, on its stream (the kernel and its dispatch); the same steps
+    # replayed from the graph, timed by events around the replays, run about
+    # 3% longer per launch (kernel_ms.graph_replay_mean_ms)
+    graph_ms = graph_steps.event_ms / args.steps
     kernel_s = stats["mean_ms"] / 1e3
     alg = in_bytes + out_bytes
     achieved = alg / kernel_s / 1e9
@@ -265,7 +277,10 @@ def headline(args, torch, xr, fields):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
-                "alg_bytes_per_launch": alg, "kernel_ms": {k: round(v, 5) for k, v in stats.items()},
+                "alg_bytes_per_launch": alg,
+                "kernel_ms": {"graph_replay_mean_ms": round(graph_ms, 5),
+                              "event_pairs": {k: (round(v, 5) if isinstance(v, float) else v)
+                                              for k, v in stats.items()}},
                 "kernel_gpixel_s": round(out_px / kernel_s / 1e9, 2),
                 # the FP32 VALU check: instruction issue time from the counters
                 "valu": read_valu(HEADLINE_PROFILE, resolved, kernel_s),
