@@ -10,13 +10,15 @@ Infinity Cache cannot hold the working set between steps.
 Printed JSON line (one):
   value       output Gpixel/s over the K timed steps (wall clock, synchronised),
               submitted as replays of a HIP graph of the rotating launches
-              (config.value_eager_launches: the same steps launched one by one)
+              (config.value_eager_launches: K steps launched one by one, each
+              between HIP events, over their GPU time)
   roofline    the resize kernel's algorithmic bytes (each input pixel read once,
               each output pixel written once) per launch / its mean launch
-              time from HIP events, against the 8 TB/s HBM3E peak; `traffic`
-              is the HBM bytes per launch measured with rocprofv3 counters
-              (profiles/pmc_*.txt), or null if those were taken on other kernel
-              sources
+              time from HIP event pairs around the eager launches (after an
+              untimed pre-roll that leaves the GPU no idle gap), against the
+              8 TB/s HBM3E peak; `traffic` is the HBM bytes per launch from
+              the rocprofv3 counters in profiles/, or null if those were taken
+              on other kernel sources
   cpu_baseline the FP64 C oracle on a bounded sample of output rows, timed on
               all host cores (the value) and on one thread, with the host's
               CPU model; the batched comparison and every extra row carry the
@@ -60,6 +62,8 @@ FP32_PEAK_TFLOPS = 78.6  # non-packed FP32 FMA: 256 CUs x 64 lanes x 2 flops x 2
 ROTATE_BYTES = 1 << 30
 KERNEL_SOURCES = ["xr_forward.hip", "xr_backward.hip", "xr_device.hpp", "xr_buffer.hpp", "xr_internal.h"]
 HEADLINE_PROFILE = "c2_bicubic_x2_u8_rgba.md"
+# untimed launches before the per-launch statistics (see time_launches)
+PREROLL_LAUNCHES = 500
 
 
 def log(msg: str) -> None:
@@ -140,26 +144,32 @@ def profile_fields(name, alg):
 
 
 def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
-    """Run warmup + steps launches rotating over buffers; returns
-    (wall seconds of the timed steps, list of per-launch event times in ms)."""
-    for i in range(warmup):
-        launch(i % n_buffers)
-    torch.cuda.synchronize()
+    """Per-launch statistics: at least PREROLL_LAUNCHES (or `warmup`, if
+    more) untimed launches, then `steps` launches each bracketed by HIP
+    events, rotating over buffers, with no synchronisation between the two
+    (the GPU runs about 10-20% slower for the first 10-20 ms after it has
+    idled, even briefly: measured on the headline, the first groups of 100
+    ran 66-73 us against 52-57 us later whenever a synchronisation preceded
+    them, and 51-55 us throughout after 500 launches without one). Returns
+    (GPU seconds of the timed launches, first start to last end; list of
+    per-launch event times in ms). The events are created (recorded once)
+    before the warm-up."""
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    for e in starts + ends:
+        e.record()
+    for i in range(max(warmup, PREROLL_LAUNCHES)):
+        launch(i % n_buffers)
     for i in range(steps):
         starts[i].record()
         launch(i % n_buffers)
         ends[i].record()
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     # GPU time from the first launch's start to the last one's end: for
     # launches of a few microseconds this is the back-to-back rate, which
     # per-launch event pairs (dominated by dispatch latency) overstate
     time_launches.span_ms = starts[0].elapsed_time(ends[-1])
-    return wall, [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return time_launches.span_ms / 1e3, [s.elapsed_time(e) for s, e in zip(starts, ends)]
 
 
 def graph_steps(launch, n_buffers: int, steps: int, torch) -> float:
@@ -206,9 +216,11 @@ def graph_launch_us(launch, n_buffers: int, torch, reps: int = 100) -> float:
             for i in range(reps):
                 launch(i % n_buffers)
     torch.cuda.current_stream().wait_stream(stream)
-    graph.replay()
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # untimed replays first, with no synchronisation before the timed one
+    # (the GPU runs slower for a while after idling; see time_launches)
+    for _ in range(5):
+        graph.replay()
     e0.record()
     graph.replay()
     e1.record()
@@ -473,7 +485,7 @@ def batch_alg_bytes(jobs) -> int:
     return total
 
 
-def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
+def batched(torch, xr, fields, reps: int = 20, cpu: bool = True):
     dev = torch.device("cuda:0")
     jobs = fields.batch_jobs(0)
     log("generating the 256-image uneven batch (sides 64..2048, scales 0.25..4)")
@@ -489,16 +501,26 @@ def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
         for s, d, f in pairs:
             xr.resize_into(s, d, f)
 
+    def timed(run, warm):
+        """Seconds per call of `run`: `warm` untimed calls, then `reps`
+        calls between HIP events, with no synchronisation in between (the
+        GPU runs slower for a while after idling; see time_launches)."""
+        for _ in range(warm):
+            run()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps / 1e3
+
     res = {}
     # (ii) eager per-image launches
     per_image()
     torch.cuda.synchronize()
     ref = [d.clone() for _, d, _ in pairs]
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        per_image()
-    torch.cuda.synchronize()
-    res["per_image_eager"] = len(pairs) * reps / (time.perf_counter() - t0)
+    res["per_image_eager"] = len(pairs) / timed(per_image, 4)
 
     stream = torch.cuda.Stream()
     # (iii) the 256 launches captured in one graph
@@ -512,11 +534,7 @@ def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
     g_multi.replay()
     torch.cuda.synchronize()
     eq_multi = all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        g_multi.replay()
-    torch.cuda.synchronize()
-    res["per_image_graph"] = len(pairs) * reps / (time.perf_counter() - t0)
+    res["per_image_graph"] = len(pairs) / timed(g_multi.replay, 4)
 
     # (i) one persistent launch over every tile, shape from the batch
     # autotuner, captured in a graph
@@ -537,16 +555,9 @@ def batched(torch, xr, fields, reps: int = 5, cpu: bool = True):
     g_one.replay()
     torch.cuda.synchronize()
     eq_one = all(torch.equal(d, r) for (_, d, _), r in zip(pairs, ref))
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    for _ in range(reps):
-        g_one.replay()
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    res["persistent_graph"] = len(pairs) * reps / wall
-    launch_ms = ev0.elapsed_time(ev1) / reps
+    launch_s = timed(g_one.replay, 15)
+    res["persistent_graph"] = len(pairs) / launch_s
+    launch_ms = launch_s * 1e3
     cpu_res = {}
     if cpu:
         log("timing the oracle on 2 rows of every image (extrapolated)")
