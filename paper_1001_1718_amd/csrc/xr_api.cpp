@@ -613,6 +613,70 @@ int scratch_address(int dev, void **out)
     return XR_OK;
 }
 
+// Median per-launch milliseconds of each of n candidates: `groups` groups of
+// `reps` launches, each group between HIP events. Everything is enqueued
+// first and read after one synchronisation at the end, behind an untimed
+// pre-roll of about 20 ms of the first candidate: the GPU runs 10-20% slower
+// for 10-20 ms after it has idled, so waiting on every group would time every
+// candidate in that state. run(k) enqueues one launch of candidate k.
+template <typename Run>
+hipError_t time_candidates(size_t n, int32_t reps, int32_t groups, hipStream_t s, Run run,
+                           std::vector<float> &med)
+{
+    med.assign(n, 0.0f);
+    if (n == 0)
+        return hipSuccess;
+    std::vector<hipEvent_t> ev(2 * n * static_cast<size_t>(groups) + 2, nullptr);
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i)
+        e = hipEventCreate(&ev[i]);
+    // one timed launch of the first candidate sizes the pre-roll
+    if (e == hipSuccess)
+        e = run(0);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev[0], s);
+    if (e == hipSuccess)
+        e = run(0);
+    if (e == hipSuccess)
+        e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess)
+        e = hipEventSynchronize(ev[1]);
+    float one = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&one, ev[0], ev[1]);
+    const int64_t pre = std::min<int64_t>(4096, static_cast<int64_t>(20.0f / std::max(one, 1e-3f)) + 1);
+    for (int64_t i = 0; i < pre && e == hipSuccess; ++i)
+        e = run(0);
+    for (size_t k = 0; k < n && e == hipSuccess; ++k) {
+        e = run(k);  // warm-up
+        for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
+            hipEvent_t *p = &ev[2 + 2 * (k * groups + g)];
+            e = hipEventRecord(p[0], s);
+            for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
+                e = run(k);
+            if (e == hipSuccess)
+                e = hipEventRecord(p[1], s);
+        }
+    }
+    if (e == hipSuccess)
+        e = hipEventSynchronize(ev.back());
+    std::vector<float> per_group(groups);
+    for (size_t k = 0; k < n && e == hipSuccess; ++k) {
+        for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
+            const hipEvent_t *p = &ev[2 + 2 * (k * groups + g)];
+            float ms = 0.0f;
+            e = hipEventElapsedTime(&ms, p[0], p[1]);
+            per_group[g] = ms / static_cast<float>(reps);
+        }
+        std::sort(per_group.begin(), per_group.end());
+        med[k] = per_group[groups / 2];
+    }
+    for (hipEvent_t x : ev)
+        if (x)
+            (void)hipEventDestroy(x);
+    return e;
+}
+
 // Validates a batch and builds its workspace image (header and job table,
 // xr_batch_workspace_bytes(n_jobs) bytes) in host memory `host`; `order`
 // holds n_jobs indices of scratch. No device memory is touched.
@@ -1143,13 +1207,6 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         return fail_hip(e, "hipStreamIsCapturing");
     if (cs != hipStreamCaptureStatusNone)
         return fail(XR_ERR_CAPTURE, "xr_autotune called on a capturing stream");
-    hipEvent_t ev0, ev1;
-    if ((e = hipEventCreate(&ev0)) != hipSuccess)
-        return fail_hip(e, "hipEventCreate");
-    if ((e = hipEventCreate(&ev1)) != hipSuccess) {
-        (void)hipEventDestroy(ev0);
-        return fail_hip(e, "hipEventCreate");
-    }
     std::vector<xr::ResizeArgs> args(n_pairs);
     for (int32_t k = 0; k < n_pairs; ++k)
         args[k] = make_args(srcs[k], dsts[k]);
@@ -1159,42 +1216,23 @@ int xr_autotune(const xr_image *srcs, const xr_image *dsts, int32_t n_pairs, int
         next = (next + 1) % n_pairs;
         return xr::launch_forward(a, filter, src->dtype, src->channels, t, mode, s);
     };
-    float best_t = 0.0f;
-    size_t best_k = 0;
-    bool have = false;
-    std::vector<float> per_group(groups);
-    for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
-        const int32_t mode = axis_mode(*src, *dst, cand[k], filter, XR_MAP_HALF_PIXEL);
-        e = launch(cand[k], mode);  // warm-up
-        for (int32_t g = 0; g < groups && e == hipSuccess; ++g) {
-            e = hipEventRecord(ev0, s);
-            for (int32_t r = 0; r < reps && e == hipSuccess; ++r)
-                e = launch(cand[k], mode);
-            if (e == hipSuccess)
-                e = hipEventRecord(ev1, s);
-            if (e == hipSuccess)
-                e = hipEventSynchronize(ev1);
-            float ms = 0.0f;
-            if (e == hipSuccess)
-                e = hipEventElapsedTime(&ms, ev0, ev1);
-            per_group[g] = ms / static_cast<float>(reps);
-        }
-        if (e != hipSuccess)
-            break;
-        std::sort(per_group.begin(), per_group.end());
-        const float med = per_group[groups / 2];
-        const int threads = cand[k].block_w * cand[k].block_h;
-        const int best_threads = have ? cand[best_k].block_w * cand[best_k].block_h : 0;
-        if (!have || med < best_t || (med == best_t && threads < best_threads)) {
-            best_t = med;
-            best_k = k;
-            have = true;
-        }
-    }
-    (void)hipEventDestroy(ev0);
-    (void)hipEventDestroy(ev1);
+    std::vector<int32_t> modes(cand.size());
+    for (size_t k = 0; k < cand.size(); ++k)
+        modes[k] = axis_mode(*src, *dst, cand[k], filter, XR_MAP_HALF_PIXEL);
+    std::vector<float> med;
+    e = time_candidates(cand.size(), reps, groups, s, [&](size_t k) { return launch(cand[k], modes[k]); }, med);
     if (e != hipSuccess)
         return fail_hip(e, "timing a candidate");
+    float best_t = 0.0f;
+    size_t best_k = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        const int threads = cand[k].block_w * cand[k].block_h;
+        const int best_threads = cand[best_k].block_w * cand[best_k].block_h;
+        if (k == 0 || med[k] < best_t || (med[k] == best_t && threads < best_threads)) {
+            best_t = med[k];
+            best_k = k;
+        }
+    }
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         g_tuned[tune_key(filter, src->dtype, src->channels, src->width, src->height, dst->width,
