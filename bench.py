@@ -289,6 +289,8 @@ def headline(args, torch, xr, fields):
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else int(traffic),
+                # the HBM bytes the counters measured, over the same launch time
+                "measured_gbs": None if traffic is None else round(traffic / kernel_s / 1e9, 1),
                 "alg_bytes_per_launch": alg,
                 "kernel_ms": {"graph_replay_mean_ms": round(graph_ms, 5),
                               "event_pairs": {k: (round(v, 5) if isinstance(v, float) else v)
@@ -651,6 +653,8 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
             "graph_hbm_frac": round(alg / (g_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
             **profile_fields(profile, alg),
             **oracle_rate(src0, out_hw, mode, layout, mapping)}
+        if out[group][name].get("traffic"):
+            out[group][name]["measured_gbs"] = round(out[group][name]["traffic"] / k_s / 1e9, 1)
         log(f"{group} {name}: {out[group][name]}")
         del srcs, dsts
         torch.cuda.empty_cache()
