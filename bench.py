@@ -132,15 +132,19 @@ def read_pmc(name: str):
         return None
 
 
-def profile_fields(name, alg):
+def profile_fields(name, alg, seconds=None):
     """The profiles/ summary of a configuration's kernel: its name and, when it
     was taken on these kernel sources, the HBM bytes per launch it measured
-    (traffic) and their ratio to the algorithmic bytes."""
+    (traffic), their ratio to the algorithmic bytes and, given the launch
+    time, those bytes per second (measured_gbs)."""
     if not name or not os.path.exists(os.path.join(ROOT, "profiles", name)):
         return {}
     traffic = read_pmc(name)
-    return {"profile": name, "traffic": None if traffic is None else int(traffic),
-            "traffic_over_alg": None if traffic is None else round(traffic / alg, 3)}
+    out = {"profile": name, "traffic": None if traffic is None else int(traffic),
+           "traffic_over_alg": None if traffic is None else round(traffic / alg, 3)}
+    if traffic is not None and seconds:
+        out["measured_gbs"] = round(traffic / seconds / 1e9, 1)
+    return out
 
 
 def time_launches(launch, n_buffers: int, steps: int, warmup: int, torch):
@@ -314,18 +318,19 @@ def headline(args, torch, xr, fields):
     }
 
 
-def hbm_reference(torch, reps: int = 20):
+def hbm_reference(torch, reps: int = 100):
     """Plain torch kernels as achievable-bandwidth reference lines for this
     GPU: a 256 MiB fill (write only) and a 256 MiB device copy. Two rotating
-    buffers exceed the 256 MB Infinity Cache."""
+    buffers exceed the 256 MB Infinity Cache. Timed after 300 untimed calls
+    that run straight into the timed ones (the GPU runs slower for a while
+    after idling; see time_launches)."""
     dev = torch.device("cuda:0")
     n = 256 << 20
     bufs = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(3)]
 
     def timed(fn):
-        for k in range(3):
+        for k in range(300):
             fn(k & 1)
-        torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         for k in range(reps):
@@ -580,7 +585,7 @@ def batched(torch, xr, fields, reps: int = 20, cpu: bool = True):
         "persistent_gbs": round(alg / (launch_ms / 1e3) / 1e9, 1),
         "alg_bytes": alg,
         "hbm_frac": round(alg / (launch_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-        **profile_fields("c3_batch_256_uneven_u8.md", alg),
+        **profile_fields("c3_batch_256_uneven_u8.md", alg, launch_ms / 1e3),
     }
 
 
@@ -651,10 +656,8 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
             "tile": repr(tile), "buffers": n_buf,
             "back_to_back_us": round(time_launches.span_ms / steps * 1e3, 2), "graph_us": round(g_us, 2),
             "graph_hbm_frac": round(alg / (g_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-            **profile_fields(profile, alg),
+            **profile_fields(profile, alg, k_s),
             **oracle_rate(src0, out_hw, mode, layout, mapping)}
-        if out[group][name].get("traffic"):
-            out[group][name]["measured_gbs"] = round(out[group][name]["traffic"] / k_s / 1e9, 1)
         log(f"{group} {name}: {out[group][name]}")
         del srcs, dsts
         torch.cuda.empty_cache()
@@ -701,7 +704,7 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
         out[group][name] = {
             "alg_bytes": alg, "kernel_us": round(k_s * 1e6, 2), "gbs": round(alg / k_s / 1e9, 1),
             "hbm_frac": round(alg / k_s / 1e9 / HBM_PEAK_GBS, 4), "gpixel_s": round(gs.numel() / k_s / 1e9, 2),
-            **profile_fields(profile, alg)}
+            **profile_fields(profile, alg, k_s)}
         if cpu:
             rate, used, t = cpu_baseline_adjoint(g, in_hw[0], in_hw[1], mode)
             out[group][name].update({"cpu_mpx_s": round(rate / 1e6, 3), "cpu_cores": used,
@@ -726,9 +729,12 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
              if c.kernel == xr.XR_KERNEL_STRIP]
     c5_tile, _ = xr.autotune(src, dst, "bicubic", candidates=cands, reps=2, groups=3)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-    xr.resize_into(src, dst, "bicubic")
+    # about 15 ms of untimed launches straight into the timed ones (the GPU
+    # runs slower for a while after idling; see time_launches)
+    for _ in range(30):
+        xr.resize_into(src, dst, "bicubic")
     ev[0].record()
-    for _ in range(3):
+    for _ in range(10):
         xr.resize_into(src, dst, "bicubic")
     ev[1].record()
     ev[2].record()
@@ -739,7 +745,7 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
                        src_height=16384, dst_row0=r0, dst_height=32768)
     ev[3].record()
     torch.cuda.synchronize()
-    whole = ev[0].elapsed_time(ev[1]) / 3 / 1e3
+    whole = ev[0].elapsed_time(ev[1]) / 10 / 1e3
     bands = ev[2].elapsed_time(ev[3]) / 1e3
     alg = (src.numel() + dst.numel()) * 2
     out["C5"]["bicubic_x2_f16_16384"] = {
@@ -747,7 +753,7 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
         "tile": repr(c5_tile),
         "gbs": round(alg / whole / 1e9, 1), "hbm_frac": round(alg / whole / 1e9 / HBM_PEAK_GBS, 4),
         "bands_gbs": round(alg / bands / 1e9, 1), "bands_bitwise_equal": bool(torch.equal(dst, dst_b)),
-        **profile_fields("c5_bicubic_x2_f16_16384.md", alg),
+        **profile_fields("c5_bicubic_x2_f16_16384.md", alg, whole),
         **oracle_rate(src, (32768, 32768), "bicubic", "hwc")}
     log(f"C5: {out['C5']['bicubic_x2_f16_16384']}")
     del src, dst, dst_b
