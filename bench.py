@@ -763,8 +763,9 @@ def configs(torch, xr, fields, steps: int = 50, warmup: int = 5, cpu: bool = Tru
 
 def profile_workload(args, torch, xr, fields):
     """One workload launched eagerly `--steps` times with a fixed launch shape
-    (the library default, or --tile / --batch-tile), nothing captured in a
-    graph and no tuning: the command the rocprofv3 summaries in profiles/ are
+    (the library default, or --tile / --batch-tile; for the 96-plane C4
+    tensor the --tile shape is stored by a one-candidate tuning), nothing
+    captured in a graph: the command the rocprofv3 summaries in profiles/ are
     taken with. Prints one JSON line with the mean launch time from HIP
     events and the algorithmic bytes per launch."""
     dev = torch.device("cuda:0")
